@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against what the paper and mathematics fix.
+
+Nothing here compares the oracle with itself: each check uses a published
+value (Philox known answers), an exact probability computed without random
+numbers (brute-force enumeration), a closed form, a large-N limit
+(final-size relation, fixed-delay mean field, SEIRM ODE of Appendix D),
+finite differences of the oracle's own loss (which pin its tangents), or an
+invariant implied by assumptions A1-A6 (Appendix A).
+"""
+
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from oracle import enumerate as EN
+from oracle import meanfield as MF
+from oracle import oracle as O
+from synth import make_workload
+from synth.graphs import complete_pairs, to_symmetric_coo
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Philox
+def test_philox_known_answers():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox_kat.txt")) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        assert list(O.philox(v[0:4], v[4:6])) == v[6:10]
+
+
+def test_uniform_grid_and_moments():
+    us = np.array([O.uniform(7, i, 3, O_TAG_INFECT, 0, 0) for i in range(20000)])
+    k = us * 2**24
+    assert np.all(k == np.round(k)) and np.all(np.round(k).astype(np.int64) % 2 == 1)
+    assert us.min() > 0 and us.max() < 1
+    # word 0 of the counter (idx, day, tag|pop<<8, stream) gives the uniform
+    o = O.philox([5, 3, O_TAG_INFECT, 0], [7, 0])
+    assert O.uniform(7, 5, 3, O_TAG_INFECT, 0, 0) == (2 * (int(o[0]) >> 9) + 1) / 2**24
+    assert abs(us.mean() - 0.5) < 5 * np.sqrt(1 / 12 / len(us))
+    assert stats.kstest(us, "uniform").pvalue > 1e-3
+
+
+O_TAG_INIT, O_TAG_INFECT, O_TAG_MORT, O_TAG_ER = 0, 1, 2, 3
+
+
+def test_decision_frequency_matches_q():
+    # P(u < q) = q for the grid uniform, to within the grid spacing
+    us = np.array([O.uniform(11, i, 0, O_TAG_INFECT) for i in range(200000)])
+    for q in (0.013, 0.25, 0.5, 0.9):
+        f = np.mean(us < q)
+        assert abs(f - q) < 5 * np.sqrt(q * (1 - q) / len(us))
+
+
+# ---------------------------------------------------------------- ER layer
+def test_er_pairs_counts_and_uniformity():
+    n = 1000
+    a, b = O.er_pairs(n, 10.0, 123, 4)
+    assert len(a) == round(n * 10 / 2)
+    assert np.all(a != b) and a.min() >= 0 and b.min() >= 0 and max(a.max(), b.max()) < n
+    deg = np.bincount(np.concatenate([a, b]), minlength=n)
+    assert abs(deg.mean() - 10.0) < 1e-12
+    # endpoint i uniform on [0,n); j uniform on the other n-1 agents
+    assert stats.chisquare(np.bincount(a, minlength=n)).pvalue > 1e-4
+    a2, _ = O.er_pairs(n, 10.0, 123, 5)
+    assert not np.array_equal(a, a2)  # resampled each day
+
+
+# ---------------------------------------------------------------- invariants
+@pytest.fixture(scope="module")
+def c1_run():
+    wl = make_workload("c1")
+    return wl, O.run_workload(wl, want_stage=True, want_agents=True)
+
+
+def test_counts_conserved_and_monotone(c1_run):
+    wl, r = c1_run
+    c = r["counts"]
+    assert np.all(c.sum(axis=1) == wl.n_agents)
+    ever = wl.n_agents - c[:, 0]
+    assert np.all(np.diff(ever) >= 0)
+    assert np.all(np.diff(c[:, 3] + c[:, 4]) >= 0)
+    assert r["mismatch"] == 0  # stage machine == exposure-window form, every agent and day
+
+
+def test_stage_durations_and_no_reinfection(c1_run):
+    wl, r = c1_run
+    st = r["stage"]  # [K+1, N]
+    K = wl.K
+    for i in range(0, wl.n_agents, 7):
+        s = st[:, i]
+        # no agent leaves R or M, and no agent returns to S
+        rm = np.nonzero(s >= 3)[0]
+        if len(rm):
+            assert np.all(s[rm[0]:] == s[rm[0]])
+        ns = np.nonzero(s != 0)[0]
+        if len(ns):
+            assert np.all(s[ns[0]:] != 0)
+        e_days = np.nonzero(s == 1)[0]
+        i_days = np.nonzero(s == 2)[0]
+        if len(e_days) and e_days[0] > 0 and e_days[0] + 3 + 5 <= K:
+            assert len(e_days) == 3 and len(i_days) == 5
+            assert np.all(np.diff(e_days) == 1) and i_days[0] == e_days[-1] + 1
+
+
+def test_infections_only_for_susceptibles(c1_run):
+    wl, r = c1_run
+    st = r["stage"]
+    h = r["h"]
+    new_e = (st[1:] == 1) & (st[:-1] == 0)
+    assert np.array_equal(new_e, (h == 1) & (st[:-1] == 0))
+
+
+def test_r_zero_and_no_infectious_mean_nothing_happens():
+    wl = make_workload("c1", K=15)
+    r = O.run_workload(wl, R=np.zeros(wl.K, np.float32), want_agents=True)
+    assert np.all(r["lam"] == 0.0)
+    assert np.all(r["counts"][1:, 1] == 0)  # no exposures ever
+    r2 = O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=2.5,
+               S=wl.S[0], m=0.01, i0=0.0, Z=wl.Z, er_mean_deg=10, er_weight=0.5, want_agents=True)
+    assert np.all(r2["A"] == 0.0) and np.all(r2["counts"][:, 0] == wl.n_agents)
+
+
+# ---------------------------------------------------------------- closed forms for the rate
+def _forced_initial(n, want_infected, seed_range=range(5000), i0=0.5):
+    """Find a seed whose initial Bernoulli(i0) draws infect exactly the given set."""
+    for s in seed_range:
+        u = np.array([O.uniform(s, i, 0xFFFFFFFF, O_TAG_INIT) for i in range(n)])
+        if np.array_equal(u < np.float32(i0), np.asarray(want_infected, bool)):
+            return s
+    raise RuntimeError("no seed found")
+
+
+def test_star_rate_closed_form():
+    # centre 0 with 4 leaves; leaves 1..3 infectious, leaf 4 not
+    n = 5
+    pairs = (np.array([0, 0, 0, 0]), np.array([1, 2, 3, 4]))
+    wts = np.array([0.25, 0.5, 0.75, 1.0], np.float32)
+    src, dst, w = to_symmetric_coo([(pairs[0], pairs[1], wts)])
+    seed = _forced_initial(n, [0, 1, 1, 1, 0])
+    age = np.array([3, 0, 1, 2, 5], np.uint8)
+    S = np.linspace(0.3, 1.0, 8).astype(np.float32)
+    R, Z, TI = np.float32(2.0), np.float32(7.5), np.float32(0.75)
+    r = O.run(age=age, pop_offsets=[0, n], src=src, dst=dst, w=w, K=1, R=R, S=S, m=0.1, i0=0.5, Z=Z,
+              T=[0, 0, TI, 0, 0], seed=seed, want_agents=True)
+    lam = r["lam"][0]
+    # centre: sum of infectious leaf weights, receiver's susceptibility
+    expect_c = float(R) * float(S[3]) * (0.25 + 0.5 + 0.75) * float(TI) / float(Z)
+    assert lam[0] == pytest.approx(expect_c, rel=1e-15)
+    # leaves see only the centre, which is susceptible: zero rate
+    assert np.all(lam[1:] == 0.0)
+    # linear in R, exactly zero at R = 0
+    r2 = O.run(age=age, pop_offsets=[0, n], src=src, dst=dst, w=w, K=1, R=2 * R, S=S, m=0.1, i0=0.5, Z=Z,
+               T=[0, 0, TI, 0, 0], seed=seed, want_agents=True)
+    assert r2["lam"][0][0] == pytest.approx(2 * expect_c, rel=1e-15)
+
+
+def test_edge_order_does_not_matter():
+    wl = make_workload("c3", n_agents=3000, K=12)
+    perm = np.random.default_rng(3).permutation(wl.n_edges)
+    r1 = O.run_workload(wl, want_agents=True)
+    r2 = O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src[perm], dst=wl.dst[perm], w=wl.w[perm],
+               K=wl.K, R=wl.R[0], S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=wl.Z, want_agents=True)
+    # weights lie on the 2^-24 grid, so the double sums are exact in any order
+    assert np.array_equal(r1["A"], r2["A"]) and np.array_equal(r1["counts"], r2["counts"])
+
+
+# ---------------------------------------------------------------- brute force
+TINY = {
+    "pair": (2, [(0, 1, 1.0)]),
+    "path4": (4, [(0, 1, 1.0), (1, 2, 0.5), (2, 3, 1.0)]),
+    "star5": (5, [(0, 1, 1.0), (0, 2, 1.0), (0, 3, 0.5), (0, 4, 0.25)]),
+    "tri_pendant": (4, [(0, 1, 1.0), (1, 2, 1.0), (0, 2, 0.75), (2, 3, 1.0)]),
+    "k4": (4, [(a, b, 1.0) for a in range(4) for b in range(a + 1, 4)]),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TINY))
+def test_monte_carlo_matches_exact_distribution(name):
+    n, und = TINY[name]
+    a = np.array([e[0] for e in und])
+    b = np.array([e[1] for e in und])
+    wts = np.array([e[2] for e in und], np.float32)
+    src, dst, w = to_symmetric_coo([(a, b, wts)])
+    age = (np.arange(n) * 3 % 8).astype(np.uint8)
+    S = np.linspace(0.4, 1.0, 8).astype(np.float32)
+    R, Z, m, i0 = np.float32(3.0), np.float32(2.0), np.float32(0.3), np.float32(0.3)
+    T = np.array([0, 0.5, 1, 0, 0], np.float32)  # presymptomatic transmission too
+    tE, tI, K = 1, 2, 9
+    edges = [(int(s), int(d), float(x)) for s, d, x in zip(src, dst, w)]
+    final, exp_drm, _ = EN.exact_distribution(n, edges, age, [float(R)] * K, [float(x) for x in S],
+                                              [float(x) for x in T], float(m), float(i0), float(Z), tE, tI, K)
+    reps = 12000
+    obs = {}
+    drm = np.zeros((reps, K))
+    for s in range(reps):
+        r = O.run(age=age, pop_offsets=[0, n], src=src, dst=dst, w=w, K=K, R=R, S=S, m=m, i0=i0, Z=Z, T=T,
+                  tau_E=tE, tau_I=tI, seed=99, stream=s, want_stage=True)
+        key = tuple(int(x) for x in r["stage"][-1])
+        obs[key] = obs.get(key, 0) + 1
+        drm[s] = r["drm"]
+    assert sum(final.values()) == pytest.approx(1.0, abs=1e-12)
+    assert set(obs) <= set(final)
+    keys = sorted(final, key=lambda k: -final[k])
+    exp_counts = np.array([final[k] * reps for k in keys])
+    obs_counts = np.array([obs.get(k, 0) for k in keys], float)
+    big = exp_counts >= 5
+    e_b = np.append(exp_counts[big], exp_counts[~big].sum())
+    o_b = np.append(obs_counts[big], obs_counts[~big].sum())
+    if e_b[-1] < 5:
+        e_b[-2] += e_b[-1]; o_b[-2] += o_b[-1]
+        e_b, o_b = e_b[:-1], o_b[:-1]
+    assert stats.chisquare(o_b, e_b).pvalue > 1e-3
+    se = drm.std(axis=0, ddof=1) / np.sqrt(reps) + 1e-12
+    assert np.all(np.abs(drm.mean(axis=0) - np.array(exp_drm)) <= 5 * se + 1e-9)
+
+
+# ---------------------------------------------------------------- large-N limits
+def _complete_runs(N, K, R, S, seeds, T=(0, 0, 1, 0, 0), m=0.01, i0=0.02):
+    a, b = complete_pairs(N)
+    src, dst, w = to_symmetric_coo([(a, b, 1.0)])
+    age = (np.arange(N) % 8).astype(np.uint8)
+    Z = np.float32(5 * (N - 1))
+    out = []
+    for s in seeds:
+        out.append(O.run(age=age, pop_offsets=[0, N], src=src, dst=dst, w=w, K=K, R=R, S=S, m=m, i0=i0, Z=Z,
+                         T=T, seed=s, want_stage=True))
+    return age, out
+
+
+@pytest.fixture(scope="module")
+def complete_graph_runs():
+    N, K = 1200, 110
+    S = np.array([0.5, 0.6, 0.7, 0.8, 0.9, 1.0, 0.55, 0.95], np.float32)
+    age, runs = _complete_runs(N, K, np.float32(2.5), S, range(12))
+    return N, K, S, age, runs
+
+
+def test_final_size_relation(complete_graph_runs):
+    N, K, S, age, runs = complete_graph_runs
+    sizes = np.bincount(age, minlength=8)
+    fin = []
+    x0 = []
+    for r in runs:
+        st = r["stage"]
+        assert r["counts"][-1, 1] + r["counts"][-1, 2] == 0  # epidemic over
+        fin.append(np.bincount(age[st[-1] == 0], minlength=8))
+        x0.append(np.bincount(age[st[0] == 2], minlength=8))
+    fin = np.mean(fin, axis=0)
+    x0 = np.mean(x0, axis=0)
+    pred = MF.final_size(2.5, S, sizes - x0, x0.sum(), N)
+    # per age group, the escaping fraction follows exp(-R S_a (N - S_inf)/(N-1))
+    assert np.all(np.abs(fin - pred) <= 0.04 * sizes)
+    assert abs(fin.sum() - pred.sum()) <= 0.02 * N
+
+
+def test_mean_field_curve(complete_graph_runs):
+    N, K, S, age, runs = complete_graph_runs
+    sizes = np.bincount(age, minlength=8)
+    x0 = np.mean([np.bincount(age[r["stage"][0] == 2], minlength=8) for r in runs], axis=0)
+    S_mf, drm_mf = MF.mean_field(2.5, S, sizes, x0, N, K, 3, 5, 0.01)
+    S_mc = np.mean([r["counts"][:, 0] for r in runs], axis=0)
+    assert np.max(np.abs(S_mc - S_mf)) <= 0.04 * N
+    c_mc = np.cumsum(np.mean([r["drm"] for r in runs], axis=0))
+    assert np.max(np.abs(c_mc - np.cumsum(drm_mf))) <= 0.04 * N
+
+
+def test_presymptomatic_transmission_scales_final_size():
+    # T_E > 0 adds T_E tau_E / tau_I to the reproduction number
+    N, K = 800, 120
+    S = np.ones(8, np.float32)
+    age, runs = _complete_runs(N, K, np.float32(1.2), S, range(8), T=(0, 0.5, 1.0, 0, 0))
+    fin = np.mean([r["counts"][-1, 0] for r in runs])
+    x0 = np.mean([r["counts"][0, 2] for r in runs])
+    pred = MF.final_size(1.2, [1.0], [N - x0], x0, N, T_I=1.0, T_E=0.5)[0]
+    pred_wrong = MF.final_size(1.2, [1.0], [N - x0], x0, N, T_I=1.0, T_E=0.0)[0]
+    assert abs(fin - pred) <= 0.03 * N
+    assert abs(fin - pred_wrong) > 0.1 * N
+
+
+def test_seirm_ode_limit():
+    # homogeneous susceptibility: same final size as the SEIRM ODE with R0 = R
+    N, K = 1200, 110
+    S = np.ones(8, np.float32)
+    age, runs = _complete_runs(N, K, np.float32(2.0), S, range(8))
+    x0 = np.mean([r["counts"][0, 2] for r in runs])
+    ode = MF.seirm_ode(2.0, N, x0, 3, 5, 0.01, 400)
+    fin_abm = np.mean([r["counts"][-1, 0] for r in runs])
+    assert abs(ode[-1, 0] - fin_abm) <= 0.02 * N
+    # deaths: m times everyone ever removed, both models
+    dead_abm = np.mean([r["counts"][-1, 4] for r in runs])
+    assert abs(dead_abm - ode[-1, 4]) <= 5 * np.sqrt(0.01 * (N - fin_abm) / len(runs)) + 1.0
+    # the fixed-delay and exponential-delay epidemics differ in shape but
+    # not in order of magnitude of the timing
+    peak_abm = np.argmax(np.mean([r["counts"][:, 2] for r in runs], axis=0))
+    peak_ode = np.argmax(ode[:, 2])
+    assert abs(int(peak_abm) - int(peak_ode)) <= 15
+
+
+# ---------------------------------------------------------------- gradients
+def _soft_setup():
+    wl = make_workload("c2", n_agents=1500, K=22)
+    tgt = np.linspace(0.0, 0.3, wl.K)
+    return wl, tgt
+
+
+def _loss(wl, tgt, R, S, m, i0, mode):
+    return O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=R, S=S,
+                 m=m, i0=i0, Z=wl.Z, mode=mode, tau_g=wl.tau_g, er_mean_deg=wl.er_mean_deg,
+                 er_weight=wl.er_weight, target=tgt)["loss"]
+
+
+def test_soft_tangents_match_finite_differences():
+    wl, tgt = _soft_setup()
+    R0, S0, m0, i00 = np.float32(2.5), wl.S[0].copy(), np.float32(0.01), np.float32(0.01)
+    dirs = O.standard_directions(wl.K, 8)
+    r = O.run_workload(wl, mode=O.SOFT, R=np.full(wl.K, R0, np.float32), target=tgt, directions=dirs)
+    g = r["dL"]
+    assert r["loss"] == pytest.approx(_loss(wl, tgt, R0, S0, m0, i00, O.SOFT), rel=0, abs=0)
+
+    def fd(k, h):
+        def at(delta):
+            R, S, m, i0 = R0, S0.copy(), m0, i00
+            if k == 0:
+                R = np.float32(R0 + delta)
+            elif k <= 8:
+                S[k - 1] = np.float32(S0[k - 1] + delta)
+            elif k == 9:
+                m = np.float32(m0 + delta)
+            else:
+                i0 = np.float32(i00 + delta)
+            return _loss(wl, tgt, R, S, m, i0, O.SOFT)
+        d1 = (at(h) - at(-h)) / (2 * h)
+        d2 = (at(h / 2) - at(-h / 2)) / h
+        return (4 * d2 - d1) / 3  # Richardson
+
+    # perturbations exactly representable in float32 around each value
+    steps = [2.0**-8] + [2.0**-12] * 8 + [2.0**-15, 2.0**-15]
+    gmax = np.max(np.abs(g))
+    for k in range(11):
+        f = fd(k, steps[k])
+        assert abs(f - g[k]) <= 1e-6 * max(abs(g[k]), 1e-3 * gmax), (k, f, g[k])
+
+
+def test_hard_mortality_gradient_closed_form():
+    wl = make_workload("c2", n_agents=3000, K=25)
+    tgt = np.linspace(0, 1, wl.K)
+    r = O.run_workload(wl, mode=O.HARD_ST, target=tgt, directions=O.standard_directions(wl.K, 8))
+    D = r["deaths"]
+    expect = 2.0 / wl.K * np.sum((D - tgt) * r["drm"])
+    assert r["dL"][9] == pytest.approx(expect, rel=1e-13)
+    # PLAIN and HARD_ST follow the same trajectory
+    r0 = O.run_workload(wl, mode=O.PLAIN, target=tgt)
+    assert np.array_equal(r0["counts"], r["counts"]) and r0["loss"] == r["loss"]
+
+
+def test_two_agent_straight_through_gradient_by_hand():
+    # agent 0 starts infectious, agent 1 susceptible; tau_E = tau_I = 1, K = 3
+    seed = _forced_initial(2, [1, 0])
+    src, dst, w = to_symmetric_coo([(np.array([0]), np.array([1]), np.array([0.75], np.float32))])
+    age = np.array([2, 5], np.uint8)
+    S = np.linspace(0.3, 1.0, 8).astype(np.float32)
+    R, Z, m, tau = 1.5, 0.5, 0.25, 0.5
+    tgt = np.array([0.1, 0.0, 0.2])
+    r = O.run(age=age, pop_offsets=[0, 2], src=src, dst=dst, w=w, K=3, R=R, S=S, m=m, i0=0.5, Z=Z, tau_E=1,
+              tau_I=1, mode=O.HARD_ST, tau_g=tau, seed=seed, target=tgt, directions=O.standard_directions(3, 8),
+              want_agents=True)
+    lam = R * float(S[5]) * 0.75 / Z
+    q = -np.expm1(-lam)
+    u = O.uniform(seed, 1, 0, O_TAG_INFECT)
+    h = float(u < q)
+    z = (np.log(q / (1 - q)) + np.log((1 - u) / u)) / tau
+    y = 1 / (1 + np.exp(-z))
+    dydl = y * (1 - y) / (tau * q)
+    # deaths: day 0 removes agent 0 (initial), day 2 removes agent 1 if exposed on day 0
+    D = np.array([m * 1.0, 0.0, m * h])
+    assert np.allclose(r["deaths"], D, rtol=0, atol=1e-15)
+    res = D - tgt
+    dL_dR = 2 / 3 * res[2] * m * dydl * float(S[5]) * 0.75 / Z
+    dL_dS5 = 2 / 3 * res[2] * m * dydl * R * 0.75 / Z
+    dL_dm = 2 / 3 * (res[0] * 1.0 + res[2] * h)
+    assert r["dL"][0] == pytest.approx(dL_dR, rel=1e-12)
+    assert r["dL"][1 + 5] == pytest.approx(dL_dS5, rel=1e-12)
+    assert r["dL"][9] == pytest.approx(dL_dm, rel=1e-12)
+    for a in (0, 1, 2, 3, 4, 6, 7):
+        assert r["dL"][1 + a] == 0.0
