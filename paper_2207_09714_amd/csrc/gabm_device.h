@@ -1,0 +1,158 @@
+// Device-side building blocks of the gabm library (gfx950, wave64).
+//
+// Counter-based generator, relaxed Bernoulli sample, packed agent records,
+// the kernel-argument views of the graph and parameters, and wave/block
+// reductions.  Everything here is for the GPU path only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gabm {
+
+constexpr int kBlock = 256;      // threads per block of every tile kernel
+constexpr int kWave = 64;
+constexpr int kTileCap = 2048;   // contacts staged in LDS per tile
+constexpr int kTileRows = 256;   // receivers per tile (one thread each in the epilogue)
+constexpr int kSlots = 64;       // spread of global FP64 accumulators (contention)
+constexpr int kCnt = 8;          // per-day aggregates: S,E,I,R,M snapshot counts, removals, spare x2
+constexpr uint32_t kDayInit = 0xFFFFFFFFu;
+
+enum : uint32_t { ST_S = 0, ST_E = 1, ST_I = 2, ST_R = 3, ST_M = 4 };
+enum : uint32_t { TAG_INIT = 0, TAG_INFECT = 1, TAG_MORT = 2, TAG_ER = 3 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 32x32->64 multiplications with a Weyl-sequence key schedule.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t a = c.x, b = c.z;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, a), lo0 = 0xD2511F53u * a;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, b), lo1 = 0xCD9E8D57u * b;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+struct Rng {
+  uint32_t k0, k1;  // key = seed
+};
+
+__device__ __forceinline__ uint4 rng_block(Rng g, uint32_t idx, uint32_t day, uint32_t tag, uint32_t pop,
+                                           uint32_t stream) {
+  return philox10(make_uint4(idx, day, tag | (pop << 8), stream), g.k0, g.k1);
+}
+
+// uniform on (0,1) from the top 23 bits: (2k+1)/2^24, exact in float and double
+__device__ __forceinline__ double unit_u(uint32_t x) { return (double)(2u * (x >> 9) + 1u) * 0x1p-24; }
+
+// ---------------------------------------------------------------------------
+// Relaxed Bernoulli (binary concrete): y = sigmoid((logit q + log((1-u)/u))/tau).
+__device__ __forceinline__ double sigm(double z) {
+  if (z >= 0.0) return 1.0 / (1.0 + exp(-z));
+  const double e = exp(z);
+  return e / (1.0 + e);
+}
+__device__ __forceinline__ double log_sigm(double z) { return z >= 0.0 ? -log1p(exp(-z)) : z - log1p(exp(z)); }
+
+// y and dy/dlambda for q = 1 - exp(-lambda); both 0 at lambda = 0
+__device__ __forceinline__ void relaxed_sample(double lam, double q, double u, double tau, double& y, double& dydl) {
+  if (!(q > 0.0)) {
+    y = 0.0;
+    dydl = 0.0;
+    return;
+  }
+  const double z = (log(q) + lam + (log1p(-u) - log(u))) / tau;  // log(1-q) = -lambda
+  y = sigm(z);
+  dydl = exp(log_sigm(z) - log(q)) * sigm(-z) / tau;
+}
+
+// y0 and dy0/di0 of the relaxed initial infection
+__device__ __forceinline__ void relaxed_init(double i0, double u, double tau, double& y0, double& dy0) {
+  const double z = (log(i0) - log1p(-i0) + (log1p(-u) - log(u))) / tau;
+  y0 = sigm(z);
+  dy0 = y0 * sigm(-z) / (tau * i0 * (1.0 - i0));
+}
+
+// ---------------------------------------------------------------------------
+// Packed hard record: stage | timer << 8 | (int16) exposure day << 16.
+__device__ __forceinline__ uint32_t rec_stage(uint32_t r) { return r & 0xFFu; }
+__device__ __forceinline__ uint32_t rec_timer(uint32_t r) { return (r >> 8) & 0xFFu; }
+__device__ __forceinline__ uint32_t make_rec(uint32_t st, uint32_t tm, int eday) {
+  return st | (tm << 8) | ((uint32_t)(uint16_t)(int16_t)eday << 16);
+}
+
+// ---------------------------------------------------------------------------
+// Kernel-argument views.
+struct DGraph {
+  const int64_t* row_ptr;  // [N+1]
+  const int32_t* col;      // [E] sender of each contact, rows = receivers
+  const float* w;          // [E]
+  const int32_t* tile_row; // [n_tiles+1]
+  const uint8_t* age;      // [N]
+  const uint16_t* pop_of;  // [N]
+  const int32_t* pop_off;  // [n_pops+1]
+  const int64_t* er_off;   // [n_pops+1] prefix of daily random pairs per population
+  int32_t N, n_pops, n_tiles;
+  int64_t er_total;        // pairs per day, all populations
+  double er_mean;
+  float er_w;
+};
+
+struct DParams {
+  const float* R;   // [n_sets*K]
+  const float* S;   // [n_sets*n_age]
+  const float* m;   // [n_sets]
+  const float* i0;  // [n_sets]
+  const float* Z;   // [n_pops]
+  double TE, TI, tau;
+  int32_t K, tau_E, tau_I, n_age, mode, per_pop, n_sets;
+};
+
+// lambda = R * S[a] * A / Z evaluated left to right in double precision
+__device__ __forceinline__ double rate(double R, double S, double A, double Z) { return R * S * A / Z; }
+
+// ---------------------------------------------------------------------------
+// Reductions.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// sum over the block of 256 threads; every thread receives the result.
+// `scratch` holds at least kBlock/kWave values.
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) scratch[wv] = v;
+  __syncthreads();
+  T s = scratch[0];
+#pragma unroll
+  for (int k = 1; k < kBlock / kWave; ++k) s += scratch[k];
+  return s;
+}
+
+__device__ __forceinline__ int pop_of_agent(const DGraph& G, int i) { return G.n_pops == 1 ? 0 : (int)G.pop_of[i]; }
+
+// one bit per agent, 64-bit words; OR the ballot of 64 consecutive agents
+// starting at `base` into the mask
+__device__ __forceinline__ void or_ballot(unsigned long long* mask, int base, unsigned long long bits) {
+  if (bits == 0ull) return;
+  const int wd = base >> 6, sh = base & 63;
+  atomicOr(&mask[wd], bits << sh);
+  if (sh) {
+    const unsigned long long hi = bits >> (64 - sh);
+    if (hi) atomicOr(&mask[wd + 1], hi);
+  }
+}
+
+__device__ __forceinline__ uint32_t mask_bit(const uint32_t* mask32, int c) { return (mask32[c >> 5] >> (c & 31)) & 1u; }
+
+}  // namespace gabm

@@ -1,0 +1,76 @@
+// Host-side internals shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/gabm.h"
+#include "gabm_device.h"
+
+namespace gabm {
+
+void set_error(const std::string& msg);
+
+// RAII-free device buffer helpers (the library frees explicitly).
+template <typename T>
+inline hipError_t dalloc(T** p, size_t n) {
+  if (n == 0) n = 1;
+  return hipMalloc((void**)p, n * sizeof(T));
+}
+
+struct Graph {
+  int32_t N = 0, n_pops = 0, n_age = 0;
+  int64_t E = 0;
+  int32_t max_degree = 0, n_tiles = 0, n_long = 0;
+  double weight_sum = 0.0;
+  std::vector<int32_t> pop_off_h;   // [n_pops+1]
+  std::vector<int64_t> er_off_h;    // [n_pops+1]
+  float er_mean = 0.f, er_w = 0.f;
+  // device
+  int64_t* row_ptr = nullptr;
+  int32_t* col = nullptr;
+  float* w = nullptr;
+  int32_t* tile_row = nullptr;
+  uint8_t* age = nullptr;
+  uint16_t* pop_of = nullptr;
+  int32_t* pop_off = nullptr;
+  int64_t* er_off = nullptr;
+
+  DGraph view() const {
+    DGraph g;
+    g.row_ptr = row_ptr; g.col = col; g.w = w; g.tile_row = tile_row; g.age = age; g.pop_of = pop_of;
+    g.pop_off = pop_off; g.er_off = er_off; g.N = N; g.n_pops = n_pops; g.n_tiles = n_tiles;
+    g.er_total = er_off_h.empty() ? 0 : er_off_h.back();
+    g.er_mean = er_mean; g.er_w = er_w;
+    return g;
+  }
+  void release();
+};
+
+// checks the parameter block against the graph; fills `out` (kernel view)
+gabm_status check_params(const Graph& G, const gabm_params* p, DParams* out);
+
+#define GABM_HIP(call)                                                        \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess) {                                                   \
+      ::gabm::set_error(std::string(#call) + ": " + hipGetErrorString(e_));   \
+      return GABM_EHIP;                                                       \
+    }                                                                         \
+  } while (0)
+
+#define GABM_CHECK(cond, code, msg) \
+  do {                              \
+    if (!(cond)) {                  \
+      ::gabm::set_error(msg);       \
+      return code;                  \
+    }                               \
+  } while (0)
+
+}  // namespace gabm
+
+struct gabm_graph_s {
+  gabm::Graph g;
+};

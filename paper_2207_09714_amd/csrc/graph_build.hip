@@ -1,0 +1,441 @@
+// Contact-graph build: directed COO -> CSR with rows = receivers, each row
+// sorted by (sender, weight); tile schedule for the transmission kernels;
+// per-agent population table; symmetry check.
+//
+// The model treats interaction networks as (sparse) adjacency matrices and
+// aggregates contacts with a permutation-invariant sum (Section 3.1 and
+// Appendix A); the adjoint of that sum is a gather over the transpose, which
+// for a symmetric contact graph is the same CSR.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "gabm_internal.h"
+
+namespace gabm {
+
+enum : uint32_t { BAD_ID = 1, BAD_SELF = 2, BAD_POP = 4, BAD_W = 8, BAD_AGE = 16, BAD_SYM = 32 };
+
+__device__ __forceinline__ int pop_search(const int32_t* off, int n_pops, int i) {
+  int lo = 0, hi = n_pops;  // off[lo] <= i < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= i) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_validate(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                           const float* __restrict__ w, int64_t E, int32_t N, const int32_t* pop_off, int n_pops,
+                           uint32_t* flag) {
+  uint32_t bad = 0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = src[e], d = dst[e];
+    if (s < 0 || s >= N || d < 0 || d >= N) { bad |= BAD_ID; continue; }
+    if (s == d) bad |= BAD_SELF;
+    if (n_pops > 1 && pop_search(pop_off, n_pops, s) != pop_search(pop_off, n_pops, d)) bad |= BAD_POP;
+    if (w) {
+      const float x = w[e];
+      if (!(x >= 0.f) || !isfinite(x)) bad |= BAD_W;
+    }
+  }
+  if (bad) atomicOr(flag, bad);
+}
+
+__global__ void k_validate_age(const uint8_t* age, int32_t N, int n_age, uint32_t* flag) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    if (age[i] >= n_age) atomicOr(flag, (uint32_t)BAD_AGE);
+}
+
+// histogram of receivers (both directions when symmetrising)
+__global__ void k_degree(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, int64_t E, int sym,
+                         unsigned long long* deg) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+    atomicAdd(&deg[dst[e]], 1ull);
+    if (sym) atomicAdd(&deg[src[e]], 1ull);
+  }
+}
+
+// ---- exclusive scan of N+1 counts (three passes; block = 256 x 8 items)
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long* sh,
+                                                              unsigned long long* total) {
+  // inclusive wave scan
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  unsigned long long x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    unsigned long long y = __shfl_up(x, off);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wv] = x;
+  __syncthreads();
+  unsigned long long pre = 0, tot = 0;
+  for (int k = 0; k < kBlock / kWave; ++k) {
+    if (k < wv) pre += sh[k];
+    tot += sh[k];
+  }
+  __syncthreads();
+  *total = tot;
+  return pre + x - v;
+}
+
+__global__ void k_scan_tiles(const unsigned long long* in, int64_t n, unsigned long long* out,
+                             unsigned long long* tile_sums) {
+  __shared__ unsigned long long sh[kBlock / kWave];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  unsigned long long v[kScanItems], s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0ull;
+    s += v[k];
+  }
+  unsigned long long tot;
+  unsigned long long pre = block_excl_scan(s, sh, &tot);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = pre;
+    pre += v[k];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_sums(unsigned long long* sums, int64_t n) {
+  __shared__ unsigned long long sh[kBlock / kWave];
+  unsigned long long carry = 0;
+  for (int64_t b = 0; b < n; b += kBlock) {
+    const int64_t i = b + threadIdx.x;
+    const unsigned long long v = i < n ? sums[i] : 0ull;
+    unsigned long long tot;
+    const unsigned long long ex = block_excl_scan(v, sh, &tot);
+    if (i < n) sums[i] = carry + ex;
+    carry += tot;
+    __syncthreads();
+  }
+}
+
+__global__ void k_scan_add(unsigned long long* out, int64_t n, const unsigned long long* sums, int64_t* row_ptr,
+                           unsigned long long* cursor) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const unsigned long long add = sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) {
+      const unsigned long long v = out[base + k] + add;
+      row_ptr[base + k] = (int64_t)v;
+      cursor[base + k] = v;
+    }
+}
+
+// scatter contacts into their receiver rows (order inside a row is fixed by
+// the sort that follows)
+__global__ void k_scatter(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                          const float* __restrict__ w, int64_t E, int sym, unsigned long long* cursor,
+                          int32_t* col, float* wout) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t s = src[e], d = dst[e];
+    const float x = w ? w[e] : 1.0f;
+    unsigned long long p = atomicAdd(&cursor[d], 1ull);
+    col[p] = s;
+    wout[p] = x;
+    if (sym) {
+      p = atomicAdd(&cursor[s], 1ull);
+      col[p] = d;
+      wout[p] = x;
+    }
+  }
+}
+
+__device__ __forceinline__ unsigned long long edge_key(int32_t c, float w) {
+  return ((unsigned long long)(uint32_t)c << 32) | (unsigned long long)__float_as_uint(w);
+}
+
+// rows of up to 32 contacts: one thread, insertion sort in place
+__global__ void k_sort_short(const int64_t* row_ptr, int32_t N, int32_t* col, float* w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t a = row_ptr[i], b = row_ptr[i + 1];
+  if (b - a < 2 || b - a > 32) return;
+  for (int64_t x = a + 1; x < b; ++x) {
+    const int32_t c = col[x];
+    const float f = w[x];
+    const unsigned long long k = edge_key(c, f);
+    int64_t y = x - 1;
+    while (y >= a && edge_key(col[y], w[y]) > k) {
+      col[y + 1] = col[y];
+      w[y + 1] = w[y];
+      --y;
+    }
+    col[y + 1] = c;
+    w[y + 1] = f;
+  }
+}
+
+constexpr int kSortLds = 4096;
+
+// rows longer than 32: one block per row, bitonic sort of the packed keys in
+// LDS (rows up to kSortLds) or in a global scratch area (longer rows)
+__global__ void __launch_bounds__(kBlock) k_sort_long(const int64_t* row_ptr, const int32_t* rows, int n_rows,
+                                                      int32_t* col, float* w, unsigned long long* gscratch,
+                                                      int64_t gscratch_len) {
+  __shared__ unsigned long long sk[kSortLds];
+  const int i = rows[blockIdx.x];
+  const int64_t a = row_ptr[i], b = row_ptr[i + 1];
+  const int64_t n = b - a;
+  int64_t P = 1;
+  while (P < n) P <<= 1;
+  unsigned long long* keys = (P <= kSortLds) ? sk : gscratch;
+  if (P > kSortLds && P > gscratch_len) return;  // host guarantees capacity
+  for (int64_t x = threadIdx.x; x < P; x += kBlock) keys[x] = x < n ? edge_key(col[a + x], w[a + x]) : ~0ull;
+  __syncthreads();
+  for (int64_t k = 2; k <= P; k <<= 1) {
+    for (int64_t j = k >> 1; j > 0; j >>= 1) {
+      for (int64_t x = threadIdx.x; x < P; x += kBlock) {
+        const int64_t y = x ^ j;
+        if (y > x) {
+          const unsigned long long kx = keys[x], ky = keys[y];
+          const bool up = (x & k) == 0;
+          if ((kx > ky) == up) {
+            keys[x] = ky;
+            keys[y] = kx;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int64_t x = threadIdx.x; x < n; x += kBlock) {
+    const unsigned long long kk = keys[x];
+    col[a + x] = (int32_t)(kk >> 32);
+    w[a + x] = __uint_as_float((uint32_t)kk);
+  }
+}
+
+__device__ __forceinline__ int64_t lower_key(const int32_t* col, const float* w, int64_t a, int64_t b,
+                                             unsigned long long k) {
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    if (edge_key(col[mid], w[mid]) < k) a = mid + 1; else b = mid;
+  }
+  return a;
+}
+
+// symmetric iff for every stored (i <- j, w) the multiplicity of (j, w) in
+// row i equals the multiplicity of (i, w) in row j
+__global__ void k_check_sym(const int64_t* row_ptr, const int32_t* col, const float* w, int32_t N, uint32_t* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int64_t a = row_ptr[i], b = row_ptr[i + 1];
+  int64_t x = a;
+  while (x < b) {
+    const int32_t j = col[x];
+    const float f = w[x];
+    int64_t y = x + 1;
+    while (y < b && col[y] == j && w[y] == f) ++y;
+    const int64_t mult = y - x;
+    const int64_t ja = row_ptr[j], jb = row_ptr[j + 1];
+    const unsigned long long k = edge_key(i, f);
+    const int64_t lo = lower_key(col, w, ja, jb, k);
+    const int64_t hi = lower_key(col, w, ja, jb, k + 1);
+    if (hi - lo != mult) {
+      atomicOr(flag, (uint32_t)BAD_SYM);
+      return;
+    }
+    x = y;
+  }
+}
+
+__global__ void k_pop_of(const int32_t* pop_off, int n_pops, int32_t N, uint16_t* pop_of) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
+    pop_of[i] = (uint16_t)pop_search(pop_off, n_pops, i);
+}
+
+__global__ void k_weight_sum(const float* w, int64_t E, double* out) {
+  __shared__ double sh[kBlock / kWave];
+  double s = 0.0;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < E; e += (int64_t)gridDim.x * blockDim.x)
+    s += (double)w[e];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) atomicAdd(out, s);
+}
+
+void Graph::release() {
+  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(age); hipFree(pop_of); hipFree(pop_off);
+  hipFree(er_off);
+  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; age = nullptr; pop_of = nullptr;
+  pop_off = nullptr; er_off = nullptr;
+}
+
+static int grid_for(int64_t n, int per = kBlock) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+// Greedy tiles of consecutive receivers: at most kTileRows rows and
+// kTileCap staged contacts; a row longer than kTileCap forms a tile alone.
+static void make_tiles(const std::vector<int64_t>& rp, std::vector<int32_t>& tiles, int32_t& n_long, int32_t& maxdeg) {
+  const int32_t N = (int32_t)rp.size() - 1;
+  tiles.clear();
+  tiles.push_back(0);
+  n_long = 0;
+  maxdeg = 0;
+  int32_t r = 0;
+  while (r < N) {
+    const int64_t d = rp[r + 1] - rp[r];
+    maxdeg = std::max<int32_t>(maxdeg, (int32_t)d);
+    if (d > kTileCap) {
+      ++n_long;
+      ++r;
+      tiles.push_back(r);
+      continue;
+    }
+    int32_t r1 = r + 1;
+    while (r1 < N && r1 - r < kTileRows && rp[r1 + 1] - rp[r] <= kTileCap) {
+      maxdeg = std::max<int32_t>(maxdeg, (int32_t)(rp[r1 + 1] - rp[r1]));
+      ++r1;
+    }
+    r = r1;
+    tiles.push_back(r);
+  }
+}
+
+gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
+  const int32_t N = d->n_agents;
+  const int sym = (d->flags & GABM_SYMMETRIZE) ? 1 : 0;
+  const int64_t Ein = d->n_edges;
+  const int64_t E = sym ? 2 * Ein : Ein;
+  G.N = N;
+  G.n_pops = d->n_pops;
+  G.n_age = d->n_age;
+  G.E = E;
+  G.pop_off_h.assign(d->pop_offsets, d->pop_offsets + d->n_pops + 1);
+  G.er_mean = d->er_mean_deg;
+  G.er_w = d->er_weight;
+  G.er_off_h.assign(d->n_pops + 1, 0);
+  for (int p = 0; p < d->n_pops; ++p) {
+    const int64_t np = G.pop_off_h[p + 1] - G.pop_off_h[p];
+    const int64_t M = (np >= 2 && d->er_mean_deg > 0.f) ? llround((double)np * (double)d->er_mean_deg / 2.0) : 0;
+    G.er_off_h[p + 1] = G.er_off_h[p] + M;
+  }
+
+  GABM_HIP(dalloc(&G.pop_off, d->n_pops + 1));
+  GABM_HIP(dalloc(&G.er_off, d->n_pops + 1));
+  GABM_HIP(dalloc(&G.age, N));
+  GABM_HIP(dalloc(&G.pop_of, N));
+  GABM_HIP(dalloc(&G.row_ptr, (size_t)N + 1));
+  GABM_HIP(dalloc(&G.col, E));
+  GABM_HIP(dalloc(&G.w, E));
+  GABM_HIP(hipMemcpyAsync(G.pop_off, G.pop_off_h.data(), sizeof(int32_t) * (d->n_pops + 1), hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.er_off, G.er_off_h.data(), sizeof(int64_t) * (d->n_pops + 1), hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.age, d->age, N, hipMemcpyDeviceToDevice, st));
+
+  uint32_t* flag = nullptr;
+  unsigned long long *deg = nullptr, *scan = nullptr, *sums = nullptr, *cursor = nullptr;
+  double* wsum = nullptr;
+  GABM_HIP(dalloc(&flag, 1));
+  GABM_HIP(hipMemsetAsync(flag, 0, sizeof(uint32_t), st));
+  const int64_t n1 = (int64_t)N + 1;
+  const int64_t n_scan_tiles = (n1 + kScanTile - 1) / kScanTile;
+  GABM_HIP(dalloc(&deg, n1));
+  GABM_HIP(dalloc(&scan, n1));
+  GABM_HIP(dalloc(&sums, n_scan_tiles));
+  GABM_HIP(dalloc(&cursor, n1));
+  GABM_HIP(dalloc(&wsum, 1));
+
+  auto cleanup = [&]() {
+    hipFree(flag); hipFree(deg); hipFree(scan); hipFree(sums); hipFree(cursor); hipFree(wsum);
+  };
+
+  if (Ein > 0)
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(Ein)), dim3(kBlock), 0, st, d->src, d->dst, d->w, Ein, N, G.pop_off,
+                       d->n_pops, flag);
+  hipLaunchKernelGGL(k_validate_age, dim3(grid_for(N)), dim3(kBlock), 0, st, G.age, N, d->n_age, flag);
+  uint32_t hflag = 0;
+  GABM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipStreamSynchronize(st));
+  if (hflag) {
+    cleanup();
+    if (hflag & BAD_ID) { set_error("contact with agent id outside [0, n_agents)"); return GABM_ERANGE; }
+    if (hflag & BAD_SELF) { set_error("self-contact (src == dst)"); return GABM_ERANGE; }
+    if (hflag & BAD_POP) { set_error("contact between different populations"); return GABM_ERANGE; }
+    if (hflag & BAD_AGE) { set_error("age group >= n_age"); return GABM_ERANGE; }
+    set_error("contact weight negative or not finite");
+    return GABM_EINVAL;
+  }
+
+  GABM_HIP(hipMemsetAsync(deg, 0, sizeof(unsigned long long) * n1, st));
+  if (Ein > 0)
+    hipLaunchKernelGGL(k_degree, dim3(grid_for(Ein)), dim3(kBlock), 0, st, d->src, d->dst, Ein, sym, deg);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_scan_tiles), dim3(kBlock), 0, st, deg, n1, scan, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, st, sums, n_scan_tiles);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_scan_tiles), dim3(kBlock), 0, st, scan, n1, sums, G.row_ptr, cursor);
+  if (Ein > 0)
+    hipLaunchKernelGGL(k_scatter, dim3(grid_for(Ein)), dim3(kBlock), 0, st, d->src, d->dst, d->w, Ein, sym, cursor,
+                       G.col, G.w);
+
+  std::vector<int64_t> rp(n1);
+  GABM_HIP(hipMemcpyAsync(rp.data(), G.row_ptr, sizeof(int64_t) * n1, hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipStreamSynchronize(st));
+  if (rp[N] != E) {
+    cleanup();
+    set_error("internal: row_ptr total does not match the contact count");
+    return GABM_EHIP;
+  }
+
+  // sort rows
+  hipLaunchKernelGGL(k_sort_short, dim3(grid_for(N)), dim3(kBlock), 0, st, G.row_ptr, N, G.col, G.w);
+  std::vector<int32_t> lrows, hrows;
+  int64_t hmax = 0;
+  for (int32_t i = 0; i < N; ++i) {
+    const int64_t dd = rp[i + 1] - rp[i];
+    if (dd > 32 && dd <= kSortLds) lrows.push_back(i);
+    else if (dd > kSortLds) { hrows.push_back(i); hmax = std::max(hmax, dd); }
+  }
+  int32_t* drows = nullptr;
+  unsigned long long* gscr = nullptr;
+  int64_t P = 1;
+  while (P < hmax) P <<= 1;
+  if (!lrows.empty() || !hrows.empty()) {
+    GABM_HIP(dalloc(&drows, lrows.size() + hrows.size()));
+    GABM_HIP(hipMemcpyAsync(drows, lrows.data(), sizeof(int32_t) * lrows.size(), hipMemcpyHostToDevice, st));
+    GABM_HIP(hipMemcpyAsync(drows + lrows.size(), hrows.data(), sizeof(int32_t) * hrows.size(), hipMemcpyHostToDevice, st));
+    if (!hrows.empty()) GABM_HIP(dalloc(&gscr, P));
+    if (!lrows.empty())
+      hipLaunchKernelGGL(k_sort_long, dim3((unsigned)lrows.size()), dim3(kBlock), 0, st, G.row_ptr, drows,
+                         (int)lrows.size(), G.col, G.w, gscr, (int64_t)0);
+    // rows longer than the LDS sort share one scratch area: one at a time
+    for (size_t k = 0; k < hrows.size(); ++k)
+      hipLaunchKernelGGL(k_sort_long, dim3(1), dim3(kBlock), 0, st, G.row_ptr, drows + lrows.size() + k, 1, G.col,
+                         G.w, gscr, P);
+  }
+
+  if (d->flags & GABM_CHECK_SYMMETRIC)
+    hipLaunchKernelGGL(k_check_sym, dim3(grid_for(N)), dim3(kBlock), 0, st, G.row_ptr, G.col, G.w, N, flag);
+  hipLaunchKernelGGL(k_pop_of, dim3(grid_for(N)), dim3(kBlock), 0, st, G.pop_off, d->n_pops, N, G.pop_of);
+  GABM_HIP(hipMemsetAsync(wsum, 0, sizeof(double), st));
+  if (E > 0) hipLaunchKernelGGL(k_weight_sum, dim3(grid_for(E, kBlock * 16)), dim3(kBlock), 0, st, G.w, E, wsum);
+
+  std::vector<int32_t> tiles;
+  make_tiles(rp, tiles, G.n_long, G.max_degree);
+  G.n_tiles = (int32_t)tiles.size() - 1;
+  GABM_HIP(dalloc(&G.tile_row, tiles.size()));
+  GABM_HIP(hipMemcpyAsync(G.tile_row, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipMemcpyAsync(&G.weight_sum, wsum, sizeof(double), hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipStreamSynchronize(st));
+  GABM_HIP(hipGetLastError());
+  hipFree(drows);
+  hipFree(gscr);
+  cleanup();
+  if (hflag & BAD_SYM) {
+    set_error("contact list is not symmetric");
+    return GABM_ENOTSYM;
+  }
+  return GABM_OK;
+}
+
+}  // namespace gabm
