@@ -1,0 +1,266 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable agent-based epidemic step on one MI355X.
+
+Workload (default): 1,000,000 agents; households (size 1-6), workplaces
+(5-50, 60 % coverage) and a Chung-Lu community layer (exponent 2.5, mean
+degree 15), one weight per undirected contact uniform on (0,1]; 90 days;
+SEIRM with 3 exposed and 5 infectious days; straight-through Gumbel-softmax
+(temperature 0.5); loss = MSE of daily deaths against a stored target;
+gradients w.r.t. R, the 8 age susceptibilities, mortality and the initial
+infected fraction; checkpoint every 10 days with recomputation.
+
+A step is one complete forward + backward run of all 90 days.  The value is
+contact-edges per second: (directed contacts per day) x days x simulations
+per step / wall time per step.  Also reported: the plain forward-only run on
+the same graph, the roofline position of the dominant kernel (algorithmic
+bytes per launch / measured launch duration, HIP events on the launch
+stream), HBM traffic from rocprofv3 counters when they match the current
+kernels, and the oracle's rate on the host CPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("day_kernels.hip", "tile.h", "gabm_device.h", "day_kernels.h", "batched.hip")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2207_09714_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_target(name, K):
+    import numpy as np
+
+    fn = os.path.join(ROOT, "tests", "golden", f"targets_{name}.txt")
+    if not os.path.exists(fn):
+        return None
+    v = np.array([float(l) for l in open(fn) if l.strip() and not l.startswith("#")])
+    return v[:K] if len(v) >= K else None
+
+
+def read_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on different kernel sources."""
+    fn = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    if not os.path.exists(fn):
+        return None
+    kv = {}
+    for line in open(fn):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def alg_bytes(kind: str, N: int, E: int, W: int, store_frac: float, has_er: bool) -> float:
+    """Algorithmic HBM bytes of one fused day launch (B = 1, float32 store).
+
+    Forward: col 4 + w 4 per contact; per agent row_ptr 8 + record read 4 and
+    write 4 + age 1, plus A 4 + flags 1 when the day is stored for the reverse
+    pass.  Reverse: col 4 + w 4 per contact; per agent row_ptr 8 + ring write
+    4 and read 4W + adjoint S r/w 8 + stored A 4 + flags 1 + age 1 + g 4.
+    The infectiousness bit mask (N/8 bytes) and the gathered adjoint g (4N)
+    are cache-resident and not counted per contact."""
+    if kind == "fwd":
+        b = 8.0 * E + 17.0 * N + 5.0 * N * store_frac
+    else:
+        b = 8.0 * E + (30.0 + 4.0 * W) * N
+    if has_er:
+        b += 16.0 * N
+    return b
+
+
+def cpu_baseline(wl, days: int):
+    import numpy as np
+
+    from oracle import oracle as ora
+
+    ora.build()
+    K0 = wl.K
+    wl.K = days
+    R = wl.R[0, :days].copy()
+    tgt = load_target(wl.name, K0)
+    t0 = time.perf_counter()
+    ora.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=days, R=R, S=wl.S[0],
+            m=wl.m[0], i0=wl.i0[0], Z=wl.Z, T=wl.T, tau_E=wl.tau_E, tau_I=wl.tau_I, mode=ora.HARD_ST,
+            tau_g=wl.tau_g, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight,
+            target=None if tgt is None else tgt[:days], directions=ora.standard_directions(days, 8))
+    dt = time.perf_counter() - t0
+    wl.K = K0
+    return {"value": wl.n_edges * days / dt, "unit": "edge-days/s", "cores": 1, "kind": "oracle",
+            "sample": f"{wl.name} graph, first {days} of {K0} days, hard forward with 11 forward-mode tangent "
+                      f"directions (gradients), single thread, {dt:.1f} s",
+            "host_nproc": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"])
+    ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
+                    help="eager launches with HIP-event kernel timing, or the day loop captured in hipGraphs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-days", type=int, default=8)
+    ap.add_argument("--only", choices=["diff", "plain", "copy"], default=None,
+                    help="run a single leg (for profiler runs)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2207_09714_amd import gabm
+    from synth import make_workload
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+
+    if args.only == "copy":
+        # plain copy of a known size, to scale the HBM counters
+        n = 256 * 1024 * 1024 // 4
+        x = torch.ones(n, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+
+    t_gen = time.perf_counter()
+    wl = make_workload(args.workload)
+    gen_s = time.perf_counter() - t_gen
+    g = gabm.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, n_age=8,
+                   pop_offsets=wl.pop.pop_offsets, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight)
+    info = g.info()
+    N, E, K = wl.n_agents, info["n_edges"] + 2 * info["er_pairs_per_day"], wl.K
+    W = wl.tau_E + wl.tau_I
+    has_er = info["er_pairs_per_day"] > 0
+    tgt = load_target(wl.name, K)
+    tgt_t = None if tgt is None else torch.tensor(tgt, device=dev)
+    ck = wl.ckpt_every
+    eager = args.launch == "eager"
+
+    def timed(sim, pb, backward):
+        def step():
+            sim.forward(pb, seed=wl.seed, target=tgt_t)
+            if backward:
+                sim.backward(pb, seed=wl.seed)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        if eager:
+            sim.kernel_times(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    res = {}
+    if args.only in (None, "diff"):
+        sim = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=not eager,
+                             time_kernels=eager, tau_g=wl.tau_g)
+        pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+        res["diff_s"] = timed(sim, pb, True)
+        res["kt"] = sim.kernel_times(reset=True) if eager else None
+        res["loss"] = float(sim.loss[0].item())
+        res["grad_R"] = float(sim.dR[0].sum().item())
+        res["workspace_bytes"] = sim.workspace_size()
+        del sim
+    if args.only in (None, "plain"):
+        simp = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.PLAIN, use_hip_graph=not eager, time_kernels=eager)
+        pbp = simp.params(wl.R, wl.S, wl.m, wl.i0)
+        res["plain_s"] = timed(simp, pbp, False)
+        res["kt_plain"] = simp.kernel_times(reset=True) if eager else None
+        del simp
+
+    if args.only is not None:
+        print(json.dumps({k: v for k, v in res.items()}), flush=True)
+        return
+
+    edge_days = float(E) * K
+    value = edge_days / res["diff_s"]
+    out = {
+        "metric": "contact-edges/sec fwd+bwd per simulated day & %HBM peak, batched-diff vs plain fwd",
+        "value": value,
+        "unit": "edge-days/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["diff_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: differentiable forward+backward, {N} agents, "
+                        f"{E} directed contacts per day, {K} days, checkpoint every {ck} days, 1 simulation",
+            "n_agents": N, "edges_per_day": E, "days": K, "sims_per_step": 1, "ckpt_every": ck,
+            "mode": "hard forward, straight-through gradients", "state_storage": "f32",
+            "launch": args.launch,
+        },
+        "days_per_s": K / res["diff_s"],
+        "plain_fwd": {"value": edge_days / res["plain_s"], "unit": "edge-days/s", "ms_per_run": res["plain_s"] * 1e3,
+                      "days_per_s": K / res["plain_s"]},
+        "loss": res["loss"],
+        "workspace_bytes": res["workspace_bytes"],
+        "graph_gen_s": gen_s,
+    }
+    kt = res["kt"]
+    if kt is not None and kt["fwd_launches"] > 0 and kt["bwd_launches"] > 0:
+        # first pass: K launches (the last segment stored); replay: every other segment again, stored
+        n_seg = (K + ck - 1) // ck if ck else 1
+        fwd_launches_per_step = K + (n_seg - 1) * ck
+        fwd_b = alg_bytes("fwd", N, E - 2 * info["er_pairs_per_day"], W, K / fwd_launches_per_step, has_er)
+        bwd_b = alg_bytes("bwd", N, E - 2 * info["er_pairs_per_day"], W, 1.0, has_er)
+        f_avg = kt["fwd_ms"] / kt["fwd_launches"] * 1e-3
+        b_avg = kt["bwd_ms"] / kt["bwd_launches"] * 1e-3
+        dom = "fwd" if kt["fwd_ms"] >= kt["bwd_ms"] else "bwd"
+        ab, dur = (fwd_b, f_avg) if dom == "fwd" else (bwd_b, b_avg)
+        kname = "k_day_fwd" if dom == "fwd" else "k_day_bwd"
+        achieved = ab / dur / 1e9
+        traffic = read_traffic(kname, wl.name)
+        out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "alg_bytes_per_launch": ab, "avg_launch_ms": dur * 1e3}
+        out["kernels"] = {
+            "k_day_fwd": {"launches_per_step": kt["fwd_launches"] / args.steps, "avg_ms": f_avg * 1e3,
+                          "alg_GBps": fwd_b / f_avg / 1e9},
+            "k_day_bwd": {"launches_per_step": kt["bwd_launches"] / args.steps, "avg_ms": b_avg * 1e3,
+                          "alg_GBps": bwd_b / b_avg / 1e9},
+            "share_of_step": (kt["fwd_ms"] + kt["bwd_ms"]) / args.steps / (res["diff_s"] * 1e3),
+        }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_days)
+    out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
+                            "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

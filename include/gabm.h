@@ -220,6 +220,7 @@ typedef struct {
   int32_t precision;   /* GABM_F32 or GABM_F64 storage */
   int32_t use_hip_graph; /* capture each forward segment / backward day loop in a hipGraph */
   int32_t schedule;    /* 0 = default tiles */
+  int32_t time_kernels; /* record HIP events around every fused day kernel (eager launches only) */
 } gabm_run_desc;
 
 /* Creates a simulation object on a built graph for the given parameter
@@ -281,6 +282,19 @@ gabm_status gabm_day_bwd(gabm_sim s, const gabm_params *p, const gabm_rng *rng, 
 /* Device pointers to the simulation's current hard records (gabm_rec[B*N],
  * agent-major: record of simulation b of agent i at i*B + b), for tests. */
 gabm_status gabm_sim_records(gabm_sim s, const gabm_rec **rec);
+
+/* Durations of the fused day kernels launched since the last reset, from
+ * the HIP events recorded on their launch stream when the simulation was
+ * created with time_kernels = 1 and use_hip_graph = 0.  Synchronises with the
+ * recorded events.  reset != 0 clears the record. */
+typedef struct {
+  double fwd_ms;         /* total of forward-day kernel durations */
+  int64_t fwd_launches;
+  double bwd_ms;         /* total of reverse-day kernel durations */
+  int64_t bwd_launches;
+} gabm_kernel_times;
+
+gabm_status gabm_sim_kernel_times(gabm_sim s, gabm_kernel_times *out, int32_t reset);
 
 gabm_status gabm_sim_destroy(gabm_sim s);
 

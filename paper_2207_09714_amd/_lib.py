@@ -25,7 +25,8 @@ EXPORTS = (
     "gabm_last_error", "gabm_version", "gabm_graph_build", "gabm_graph_info", "gabm_graph_csr", "gabm_graph_destroy",
     "gabm_transmit_fwd", "gabm_sample_infect", "gabm_progress_stages", "gabm_transmit_bwd",
     "gabm_param_grad_reduce", "gabm_er_daily", "gabm_sim_create", "gabm_sim_workspace_size", "gabm_sim_forward",
-    "gabm_sim_backward", "gabm_day_fwd", "gabm_day_bwd", "gabm_sim_records", "gabm_sim_destroy",
+    "gabm_sim_backward", "gabm_day_fwd", "gabm_day_bwd", "gabm_sim_records", "gabm_sim_kernel_times",
+    "gabm_sim_destroy",
 )
 
 
@@ -60,7 +61,12 @@ class Rng(C.Structure):
 
 class RunDesc(C.Structure):
     _fields_ = [("n_reps", C.c_int32), ("ckpt_every", C.c_int32), ("precision", C.c_int32),
-                ("use_hip_graph", C.c_int32), ("schedule", C.c_int32)]
+                ("use_hip_graph", C.c_int32), ("schedule", C.c_int32), ("time_kernels", C.c_int32)]
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [("fwd_ms", C.c_double), ("fwd_launches", C.c_int64), ("bwd_ms", C.c_double),
+                ("bwd_launches", C.c_int64)]
 
 
 class FwdOut(C.Structure):
@@ -104,6 +110,7 @@ def lib() -> C.CDLL:
         "gabm_day_fwd": ([vp, C.POINTER(Params), C.POINTER(Rng), i32, vp, i32, C.POINTER(FwdOut), vp], C.c_int),
         "gabm_day_bwd": ([vp, C.POINTER(Params), C.POINTER(Rng), i32, C.POINTER(Grads), vp], C.c_int),
         "gabm_sim_records": ([vp, C.POINTER(vp)], C.c_int),
+        "gabm_sim_kernel_times": ([vp, C.POINTER(KernelTimes), i32], C.c_int),
         "gabm_sim_destroy": ([vp], C.c_int),
     }
     for name, (args, res) in sig.items():

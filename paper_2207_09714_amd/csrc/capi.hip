@@ -25,6 +25,7 @@ gabm_status sim_day_fwd(Sim& s, const DParams& P, const gabm_rng* r, int day, co
                         const gabm_fwd_out* out, hipStream_t st);
 gabm_status sim_day_bwd(Sim& s, const DParams& P, const gabm_rng* r, int day, const gabm_grads* out, hipStream_t st);
 int sim_n_out(const Sim& s);
+gabm_status sim_kernel_times(Sim& s, gabm_kernel_times* out, int reset);
 
 gabm_status check_params(const Graph& G, const gabm_params* p, DParams* out) {
   GABM_CHECK(p != nullptr, GABM_EINVAL, "params is NULL");
@@ -66,11 +67,11 @@ struct StepInf {
 
 __global__ void __launch_bounds__(kBlock) k_step_gather(DGraph G, StepInf inf, double* out) {
   __shared__ TileShared sh;
-  auto ev = [&](int64_t e) -> double { return (double)G.w[e] * inf.at(G.col[e]); };
+  auto ev = [&](int c, float w) -> double { return (double)w * inf.at(c); };
   auto epi = [&](int i, double A, bool active) {
     if (active) out[i] = A;
   };
-  tile_pass(G, blockIdx.x, sh, ev, epi);
+  tile_pass(G, tile_bounds(G, blockIdx.x), sh, ev, epi);
 }
 
 __device__ __forceinline__ void er_pair_step(const DGraph& G, Rng rng, uint32_t stream, int t, int64_t k, int& gi,
@@ -473,6 +474,11 @@ gabm_status gabm_sim_records(gabm_sim s, const gabm_rec** rec) {
   GABM_CHECK(s && rec, GABM_EINVAL, "simulation or rec is NULL");
   *rec = s->s.rec[s->s.cur];
   return GABM_OK;
+}
+
+gabm_status gabm_sim_kernel_times(gabm_sim s, gabm_kernel_times* out, int32_t reset) {
+  GABM_CHECK(s && out, GABM_EINVAL, "simulation or out is NULL");
+  return sim_kernel_times(s->s, out, reset);
 }
 
 gabm_status gabm_sim_destroy(gabm_sim s) {

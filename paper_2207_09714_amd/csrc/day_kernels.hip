@@ -196,9 +196,22 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
   const int slot = blockIdx.x & (kSlots - 1);
   auto cnt_at = [&](int o) { return a.cnt + (((int64_t)o * P.K + t) * kSlots + slot) * kCnt; };
 
-  auto ev = [&](int64_t e) -> double {
-    const int c = G.col[e];
-    const double w = (double)G.w[e];
+  // per-agent inputs of the epilogue, loaded before the contact stream
+  const TileBounds tb = tile_bounds(G, blockIdx.x);
+  const bool longrow = tb.e1 - tb.e0 > kTileCap;
+  const int my_i = longrow ? tb.r0 : tb.r0 + tid;
+  const bool my_on = longrow ? tid == 0 : tid < tb.r1 - tb.r0;
+  uint32_t pre_rec = 0u;
+  int pre_age = 0;
+  double pre_aer = 0.0;
+  if (my_on) {
+    if (!SOFT) pre_rec = a.rec_in[my_i];
+    pre_age = G.age[my_i];
+    if (a.A_er) pre_aer = a.A_er[my_i];
+  }
+
+  auto ev = [&](int c, float wf) -> double {
+    const double w = (double)wf;
     if (SOFT) return w * (double)a.inf_cur[c];
     double v = P.TI * (double)mask_bit(a.mI_cur, c);
     if (a.mE_cur) v += P.TE * (double)mask_bit(a.mE_cur, c);
@@ -212,13 +225,13 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
     int p = 0;
     if (active) {
       if (a.A_er) {
-        A += a.A_er[i];
+        A += pre_aer;
         a.A_er[i] = 0.0;
       }
       p = pop_of_agent(G, i);
       const int set = set_of(P, p);
       const uint32_t loc = (uint32_t)(i - G.pop_off[p]);
-      const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + G.age[i]], Zp = P.Z[p];
+      const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + pre_age], Zp = P.Z[p];
       const double lam = rate(Rt, Sa, A, Zp);
       const double q = -expm1(-lam);
       const double u = unit_u(rng_block(a.rng, loc, (uint32_t)t, TAG_INFECT, (uint32_t)p, a.stream).x);
@@ -250,7 +263,7 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
         cS = S1; cE = wE; cI = wI; cRM = 1.0 - S1 - wE - wI;
         cD = old + (t == P.tau_I - 1 ? x0 : 0.0);
       } else {
-        const uint32_t r = a.rec_in[i];
+        const uint32_t r = pre_rec;
         const uint32_t st = rec_stage(r);
         uint32_t tm = rec_timer(r);
         const bool h = u < q;
@@ -330,7 +343,7 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
       }
     }
   };
-  tile_pass(G, blockIdx.x, sh, ev, epi);
+  tile_pass(G, tb, sh, ev, epi);
 }
 
 // ----------------------------------------------------------------- reverse day
@@ -351,16 +364,34 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
   const int o_tile = tile_output(G, P, blockIdx.x);  // == set of the tile when uniform
   const int slot = blockIdx.x & (kSlots - 1);
 
-  auto ev = [&](int64_t e) -> double {
+  // per-agent inputs of the epilogue, loaded before the contact stream
+  const TileBounds tb = tile_bounds(G, blockIdx.x);
+  const bool longrow = tb.e1 - tb.e0 > kTileCap;
+  const int my_i = longrow ? tb.r0 : tb.r0 + tid;
+  const bool my_on = longrow ? tid == 0 : tid < tb.r1 - tb.r0;
+  int pre_age = 0;
+  double pre_A = 0.0, pre_Sbar = 0.0, pre_ier = 0.0;
+  uint32_t pre_fl = 0u;
+  if (my_on) {
+    pre_age = G.age[my_i];
+    pre_Sbar = (double)a.Sbar[my_i];
+    if (t >= 1) {
+      pre_A = (double)a.A_st[my_i];
+      if (!SOFT) pre_fl = a.fl_st[my_i];
+    }
+    if (a.do_gather && a.infbar_er) pre_ier = a.infbar_er[my_i];
+  }
+
+  auto ev = [&](int c, float wf) -> double {
     if (!a.do_gather) return 0.0;
-    return (double)G.w[e] * (double)a.g_cur[G.col[e]];
+    return (double)wf * (double)a.g_cur[c];
   };
 
   auto epi = [&](int i, double infbar, bool active) {
     if (active) {
       if (a.do_gather) {
         if (a.infbar_er) {
-          infbar += a.infbar_er[i];
+          infbar += pre_ier;
           a.infbar_er[i] = 0.0;
         }
         a.ring[(int64_t)(t % W) * G.N + i] = (RT)infbar;
@@ -377,10 +408,10 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           if (k <= P.tau_E) sE += v; else sI += v;
         }
         const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + W] : 0.0;
-        const double Sbar1 = (double)a.Sbar[i];
+        const double Sbar1 = pre_Sbar;
         const double xi_bar = drm_bar + P.TI * sI + P.TE * sE - Sbar1;
-        const double A = (double)a.A_st[i];
-        const double Rt = P.R[set * P.K + d], Sa = P.S[set * P.n_age + G.age[i]], Zp = P.Z[p];
+        const double A = pre_A;
+        const double Rt = P.R[set * P.K + d], Sa = P.S[set * P.n_age + pre_age], Zp = P.Z[p];
         const double lam = rate(Rt, Sa, A, Zp);
         const double q = -expm1(-lam);
         const double u = unit_u(rng_block(a.rng, loc, (uint32_t)d, TAG_INFECT, (uint32_t)p, a.stream).x);
@@ -391,7 +422,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           Sv = (double)a.S_st[i];
           h = y;
         } else {
-          const uint32_t fl = a.fl_st[i];
+          const uint32_t fl = pre_fl;
           Sv = (double)(fl & 1u);
           h = (double)((fl >> 1) & 1u);
         }
@@ -402,10 +433,10 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           const double base = lam_bar * A / Zp;
           if (o_tile >= 0) {
             atomicAdd(&sg[0], base * Sa);
-            atomicAdd(&sg[2 + G.age[i]], base * Rt);
+            atomicAdd(&sg[2 + pre_age], base * Rt);
           } else {
             atomicAdd(&a.gR[((int64_t)set * P.K + d) * kSlots + slot], base * Sa);
-            atomicAdd(&a.gS[((int64_t)set * P.n_age + G.age[i]) * kSlots + slot], base * Rt);
+            atomicAdd(&a.gS[((int64_t)set * P.n_age + pre_age) * kSlots + slot], base * Rt);
           }
         }
       } else {
@@ -413,7 +444,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
         double sI = 0.0;
         for (int k = 0; k < P.tau_I; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
         const double x0_bar =
-            P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + P.tau_I - 1] : 0.0) - (double)a.Sbar[i];
+            P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + P.tau_I - 1] : 0.0) - pre_Sbar;
         const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, a.stream).x);
         double y0, dy0;
         relaxed_init((double)P.i0[set], u, P.tau, y0, dy0);
@@ -436,7 +467,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
       }
     }
   };
-  tile_pass(G, blockIdx.x, sh, ev, epi);
+  tile_pass(G, tb, sh, ev, epi);
 }
 
 // ----------------------------------------------------------------- closing reductions

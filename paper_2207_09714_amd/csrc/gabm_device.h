@@ -87,11 +87,20 @@ __device__ __forceinline__ uint32_t make_rec(uint32_t st, uint32_t tm, int eday)
 
 // ---------------------------------------------------------------------------
 // Kernel-argument views.
+
+// One receiver tile: rows [r0, r1), contacts [e0, e1); 32 bytes, read with
+// two independent 16-byte loads.
+struct alignas(16) TileInfo {
+  int64_t e0, e1;
+  int32_t r0, r1, pad0, pad1;
+};
+
 struct DGraph {
   const int64_t* row_ptr;  // [N+1]
   const int32_t* col;      // [E] sender of each contact, rows = receivers
   const float* w;          // [E]
   const int32_t* tile_row; // [n_tiles+1]
+  const TileInfo* tiles;   // [n_tiles]
   const uint8_t* age;      // [N]
   const uint16_t* pop_of;  // [N]
   const int32_t* pop_off;  // [n_pops+1]

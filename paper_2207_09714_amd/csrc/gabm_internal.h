@@ -33,6 +33,7 @@ struct Graph {
   int32_t* col = nullptr;
   float* w = nullptr;
   int32_t* tile_row = nullptr;
+  TileInfo* tiles = nullptr;
   uint8_t* age = nullptr;
   uint16_t* pop_of = nullptr;
   int32_t* pop_off = nullptr;
@@ -40,7 +41,7 @@ struct Graph {
 
   DGraph view() const {
     DGraph g;
-    g.row_ptr = row_ptr; g.col = col; g.w = w; g.tile_row = tile_row; g.age = age; g.pop_of = pop_of;
+    g.row_ptr = row_ptr; g.col = col; g.w = w; g.tile_row = tile_row; g.tiles = tiles; g.age = age; g.pop_of = pop_of;
     g.pop_off = pop_off; g.er_off = er_off; g.N = N; g.n_pops = n_pops; g.n_tiles = n_tiles;
     g.er_total = er_off_h.empty() ? 0 : er_off_h.back();
     g.er_mean = er_mean; g.er_w = er_w;

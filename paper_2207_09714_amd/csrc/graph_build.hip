@@ -262,9 +262,9 @@ __global__ void k_weight_sum(const float* w, int64_t E, double* out) {
 }
 
 void Graph::release() {
-  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(age); hipFree(pop_of); hipFree(pop_off);
+  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(tiles); hipFree(age); hipFree(pop_of); hipFree(pop_off);
   hipFree(er_off);
-  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; age = nullptr; pop_of = nullptr;
+  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; tiles = nullptr; age = nullptr; pop_of = nullptr;
   pop_off = nullptr; er_off = nullptr;
 }
 
@@ -424,6 +424,16 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
   G.n_tiles = (int32_t)tiles.size() - 1;
   GABM_HIP(dalloc(&G.tile_row, tiles.size()));
   GABM_HIP(hipMemcpyAsync(G.tile_row, tiles.data(), sizeof(int32_t) * tiles.size(), hipMemcpyHostToDevice, st));
+  std::vector<TileInfo> tinfo(G.n_tiles);
+  for (int32_t k = 0; k < G.n_tiles; ++k) {
+    tinfo[k].r0 = tiles[k];
+    tinfo[k].r1 = tiles[k + 1];
+    tinfo[k].e0 = rp[tiles[k]];
+    tinfo[k].e1 = rp[tiles[k + 1]];
+    tinfo[k].pad0 = tinfo[k].pad1 = 0;
+  }
+  GABM_HIP(dalloc(&G.tiles, tinfo.size()));
+  GABM_HIP(hipMemcpyAsync(G.tiles, tinfo.data(), sizeof(TileInfo) * tinfo.size(), hipMemcpyHostToDevice, st));
   GABM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GABM_HIP(hipMemcpyAsync(&G.weight_sum, wsum, sizeof(double), hipMemcpyDeviceToHost, st));
   GABM_HIP(hipStreamSynchronize(st));

@@ -18,7 +18,66 @@ static int blocks_for(int64_t n) {
 }
 static int blocks_capped(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 8192)); }
 
+hipEvent_t Sim::next_event() {
+  if (ev_used == ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ev_pool.push_back(e);
+  }
+  return ev_pool[ev_used++];
+}
+
+// brackets a launch with a pair of events when kernel timing is on
+struct KTime {
+  Sim& s;
+  hipStream_t st;
+  std::vector<std::pair<int, int>>* list;
+  int a = -1;
+  KTime(Sim& s_, hipStream_t st_, bool fwd) : s(s_), st(st_), list(fwd ? &s_.ev_fwd : &s_.ev_bwd) {
+    if (!s.time_kernels || s.use_graph) return;
+    hipEvent_t e = s.next_event();
+    if (!e) return;
+    a = (int)s.ev_used - 1;
+    hipEventRecord(e, st);
+  }
+  ~KTime() {
+    if (a < 0) return;
+    hipEvent_t e = s.next_event();
+    if (!e) return;
+    hipEventRecord(e, st);
+    list->emplace_back(a, (int)s.ev_used - 1);
+  }
+};
+
+gabm_status sim_kernel_times(Sim& s, gabm_kernel_times* out, int reset) {
+  double f = 0.0, b = 0.0;
+  for (auto& pr : s.ev_fwd) {
+    float ms = 0.f;
+    GABM_HIP(hipEventSynchronize(s.ev_pool[pr.second]));
+    GABM_HIP(hipEventElapsedTime(&ms, s.ev_pool[pr.first], s.ev_pool[pr.second]));
+    f += ms;
+  }
+  for (auto& pr : s.ev_bwd) {
+    float ms = 0.f;
+    GABM_HIP(hipEventSynchronize(s.ev_pool[pr.second]));
+    GABM_HIP(hipEventElapsedTime(&ms, s.ev_pool[pr.first], s.ev_pool[pr.second]));
+    b += ms;
+  }
+  out->fwd_ms = f;
+  out->fwd_launches = (int64_t)s.ev_fwd.size();
+  out->bwd_ms = b;
+  out->bwd_launches = (int64_t)s.ev_bwd.size();
+  if (reset) {
+    s.ev_fwd.clear();
+    s.ev_bwd.clear();
+    s.ev_used = 0;
+  }
+  return GABM_OK;
+}
+
 void Sim::release() {
+  for (hipEvent_t e : ev_pool) hipEventDestroy(e);
+  ev_pool.clear();
   for (auto& kv : fwd_graphs) hipGraphExecDestroy(kv.second);
   for (auto& kv : bwd_graphs) hipGraphExecDestroy(kv.second);
   fwd_graphs.clear();
@@ -87,6 +146,7 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
   s.n_seg = (s.K + s.ckpt - 1) / s.ckpt;
   s.precision = run->precision;
   s.use_graph = run->use_hip_graph;
+  s.time_kernels = run->time_kernels;
   s.rsz = run->precision == GABM_F64 ? 8 : 4;
   s.NB = (int64_t)G.N * s.B;
   if (s.B == 1) {
@@ -248,6 +308,7 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.S_st = (store && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.cnt = count ? s.cnt : nullptr;
   a.lam_out = nullptr;
+  KTime kt(s, st, true);
   if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_day_fwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   s.cur = 1 - s.cur;
@@ -323,6 +384,7 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.fl_st = (t >= 1 && !soft) ? s.fl_st + (int64_t)slot * s.NB : nullptr;
   a.S_st = (t >= 1 && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.Dbar = s.Dbar_eff; a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
+  KTime kt(s, st, false);
   if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_day_bwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
 }

@@ -55,6 +55,13 @@ struct Sim {
   double* gS = nullptr;   // [n_sets][n_age][kSlots]
   double* gi0 = nullptr;  // [n_sets][kSlots]
 
+  // kernel timing: event pairs around each fused day kernel
+  int32_t time_kernels = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<int, int>> ev_fwd, ev_bwd;  // indices into ev_pool
+  size_t ev_used = 0;
+  hipEvent_t next_event();
+
   int next_day = 0;     // forward progress for gabm_day_fwd
   int next_bwd = -1;    // reverse progress for gabm_day_bwd
   bool fwd_done = false;

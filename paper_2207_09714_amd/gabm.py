@@ -203,7 +203,7 @@ class Simulator:
 
     def __init__(self, graph: Graph, *, n_sets=1, K, Z, tau_E=3, tau_I=5, mode=HARD_ST, n_reps=1,
                  per_pop_params=False, ckpt_every=0, precision=F32, use_hip_graph=False, T=(0, 0, 1, 0, 0),
-                 tau_g=0.5):
+                 tau_g=0.5, time_kernels=False):
         self.graph = graph
         self.n_sets, self.K, self.n_reps = int(n_sets), int(K), int(n_reps)
         self.per_pop = bool(per_pop_params)
@@ -215,8 +215,8 @@ class Simulator:
         pb = self.params(zeros[: n_sets * K], zeros[: n_sets * graph.n_age], zeros[:n_sets] + 0.5,
                          zeros[:n_sets] + 0.5)
         run = L.RunDesc()
-        run.n_reps, run.ckpt_every, run.precision, run.use_hip_graph, run.schedule = (
-            int(n_reps), int(ckpt_every), int(precision), 1 if use_hip_graph else 0, 0)
+        run.n_reps, run.ckpt_every, run.precision, run.use_hip_graph, run.schedule, run.time_kernels = (
+            int(n_reps), int(ckpt_every), int(precision), 1 if use_hip_graph else 0, 0, 1 if time_kernels else 0)
         self._run = run
         h = C.c_void_p()
         check(lib().gabm_sim_create(graph.handle, C.byref(pb.c), C.byref(run), C.byref(h)))
@@ -293,6 +293,11 @@ class Simulator:
         g = self._grads()
         check(lib().gabm_day_bwd(self.handle, C.byref(params.c), C.byref(rng), int(day), C.byref(g),
                                  C.c_void_p(_stream(stream))))
+
+    def kernel_times(self, reset=True) -> dict:
+        kt = L.KernelTimes()
+        check(lib().gabm_sim_kernel_times(self.handle, C.byref(kt), 1 if reset else 0))
+        return {k: getattr(kt, k) for k, _ in L.KernelTimes._fields_}
 
     def records(self) -> torch.Tensor:
         p = C.c_void_p()
