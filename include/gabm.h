@@ -219,7 +219,9 @@ typedef struct {
                           many days, recomputing each segment from a state snapshot; 0 = keep all */
   int32_t precision;   /* GABM_F32 or GABM_F64 storage */
   int32_t use_hip_graph; /* capture each forward segment / backward day loop in a hipGraph */
-  int32_t schedule;    /* 0 = default tiles */
+  int32_t schedule;    /* 0: choose per simulation (persistent LDS-mask kernels when eligible:
+                          float state, one parameter set and population, up to 2^20 agents);
+                          1: receiver-tile kernels only */
   int32_t time_kernels; /* record HIP events around every fused day kernel (eager launches only) */
 } gabm_run_desc;
 

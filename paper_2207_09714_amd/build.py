@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgabm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["graph_build.hip", "day_kernels.hip", "batched.hip", "sim.hip", "capi.hip"]
+SOURCES = ["graph_build.hip", "day_kernels.hip", "day_fast.hip", "batched.hip", "sim.hip", "capi.hip"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

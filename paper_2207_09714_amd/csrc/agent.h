@@ -1,0 +1,94 @@
+// Per-agent work of one day, shared by every kernel family.
+//
+// Forward (hard state): the Bernoulli draw of Eq. 3 on the aggregate rate
+// and Progress (Section 3.1): E and I timers count down, E -> I after tau_E
+// days, I -> R or M after tau_I days (M with probability m), and a
+// susceptible agent whose draw succeeds becomes E (it cannot transmit on the
+// day of exposure, assumption A2).
+//
+// Reverse (straight-through / relaxed adjoint of one day, for one agent):
+//   xi_bar = m Dbar^{d+W} + T_I sum_{I window} inf_bar + T_E sum_{E window} inf_bar - Sbar^{d+1}
+//   Sbar^d = Sbar^{d+1} + h^d xi_bar
+//   lambda_bar = S^d xi_bar dy/dlambda,   g^d = R S_a / Z lambda_bar
+// with the window sums over the W = tau_E + tau_I following days.
+#pragma once
+
+#include "gabm_device.h"
+
+namespace gabm {
+
+struct HardDay {
+  uint32_t rec;     // next record
+  uint32_t newst;   // next stage
+  bool removed;     // I -> R or M today
+  bool h;           // the day's hard draw
+  bool was_s;       // susceptible at the start of the day
+};
+
+__device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uint32_t stream, int t, int set, int p,
+                                                  uint32_t loc, int age, double A, uint32_t r, double* lam_out) {
+  const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + age], Zp = P.Z[p];
+  const double lam = rate(Rt, Sa, A, Zp);
+  if (lam_out) *lam_out = lam;
+  const double q = -expm1(-lam);
+  const double u = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_INFECT, (uint32_t)p, stream).x);
+  HardDay o;
+  o.h = u < q;
+  const uint32_t st = rec_stage(r);
+  uint32_t tm = rec_timer(r);
+  o.was_s = st == ST_S;
+  o.removed = false;
+  o.newst = st;
+  o.rec = r;
+  if (st == ST_E || st == ST_I) {
+    tm -= 1;
+    if (tm == 0) {
+      if (st == ST_E) {
+        o.newst = ST_I;
+        tm = (uint32_t)P.tau_I;
+      } else {
+        const double um = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_MORT, (uint32_t)p, stream).x);
+        o.newst = um < (double)P.m[set] ? ST_M : ST_R;
+        o.removed = true;
+      }
+    }
+    o.rec = (r & 0xFFFF0000u) | (tm << 8) | o.newst;
+  } else if (st == ST_S && o.h) {
+    o.newst = ST_E;
+    o.rec = make_rec(ST_E, (uint32_t)P.tau_E, t);
+  }
+  return o;
+}
+
+struct AdjOut {
+  double Sbar;      // Sbar^d
+  double g;         // g^d
+  double lam_bar;
+};
+
+// One agent's adjoint of day d.  sE/sI: sums of inf_bar over the E and I
+// windows after day d; Sv, h: susceptible indicator and draw of day d (hard
+// values, or the relaxed ones in SOFT mode with `soft` set).  dy/dlambda is
+// evaluated only when it can matter (S^d != 0 and A > 0).
+__device__ __forceinline__ AdjOut agent_adjoint(const DParams& P, Rng rng, uint32_t stream, int d, int set, int p,
+                                                uint32_t loc, int age, double A, double Sv, double h, bool soft,
+                                                double sE, double sI, double Sbar1, double drm_bar) {
+  const double xi_bar = drm_bar + P.TI * sI + P.TE * sE - Sbar1;
+  const double Rt = P.R[set * P.K + d], Sa = P.S[set * P.n_age + age], Zp = P.Z[p];
+  double dydl = 0.0;
+  if (soft || (Sv != 0.0 && A > 0.0)) {
+    const double lam = rate(Rt, Sa, A, Zp);
+    const double q = -expm1(-lam);
+    const double u = unit_u(rng_block(rng, loc, (uint32_t)d, TAG_INFECT, (uint32_t)p, stream).x);
+    double y;
+    relaxed_sample(lam, q, u, P.tau, y, dydl);
+    if (soft) h = y;
+  }
+  AdjOut o;
+  o.Sbar = Sbar1 + h * xi_bar;
+  o.lam_bar = Sv * xi_bar * dydl;
+  o.g = Rt * Sa / Zp * o.lam_bar;
+  return o;
+}
+
+}  // namespace gabm

@@ -1,0 +1,319 @@
+// Split day kernels (float state, one parameter set, one population, up to
+// 2^20 agents): a persistent neighbour-sum kernel and an element-wise agent
+// kernel.
+//
+// Neighbour sum.  One 1024-thread block per compute unit; the gathered side
+// is a one-bit-per-agent mask held in LDS for the whole launch -- the
+// infectious mask in the forward, the mask of non-zero rate adjoints g in the
+// reverse pass -- so a gather costs an LDS read, and the reverse pass reads g
+// from memory only for senders whose bit is set.  Each wave streams its own
+// chunks of the contact list (see below), with loads software-pipelined
+// across chunks.  Sums are double-precision sums of the same float terms in
+// a fixed order.
+//
+// Agent pass.  One thread per agent finishes the day with the per-agent
+// functions of agent.h (Section 3.1, Eq. 1-3 and Progress; the
+// straight-through adjoint), so the serial per-agent arithmetic runs at full
+// occupancy instead of inside the streaming loop.
+#include "agent.h"
+#include "day_kernels.h"
+
+namespace gabm {
+
+__device__ __forceinline__ uint32_t lds_bit(const unsigned long long* m, int c) {
+  return (uint32_t)(m[c >> 6] >> (c & 63)) & 1u;
+}
+
+// ---------------------------------------------------------------- wave-parallel neighbour sum
+//
+// The destination-sorted contact list is cut into chunks of kChunk = 256
+// contacts; a wave owns a chunk, lane l its contacts 4l .. 4l+3 (16-byte
+// loads).  The packed sender carries, in its top byte, the number of rows
+// (receivers) that start at that contact, so an integer prefix sum over the
+// wave gives every contact's receiver and no row offsets are read.  Values
+// stay in registers: each lane sums its contacts with a restart at each row
+// start, a segmented scan over the wave carries partial sums between lanes,
+// and the lane holding a row's last contact writes the row sum.  A row that
+// crosses a chunk boundary leaves one piece per chunk (first_piece: the part
+// of the row that began before the chunk; last_piece: the part of the
+// chunk's last row that continues after it), added in chunk order by the
+// agent pass.  Waves are independent: no block barrier after the mask load.
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct WStage {
+  u32x4 p;   // packed senders of this lane's 4 contacts
+  f32x4 w;
+  uint32_t pn;  // packed sender of the following contact (an artificial row start after the list)
+  f32x4 g;   // reverse: adjoints of the senders whose mask bit is set, else 0
+};
+
+__device__ __forceinline__ void wstage_load(const DGraph& G, WStage& s, int64_t k) {
+  const int lane = threadIdx.x & 63;
+  const int64_t base = k * kChunk + lane * 4;
+  const int64_t npad = G.n_chunks * kChunk;
+  s.p = __builtin_nontemporal_load((const u32x4*)(G.colp + base));
+  s.w = __builtin_nontemporal_load((const f32x4*)(G.wp + base));
+  const int64_t nx = base + 4;
+  const uint32_t pv = G.colp[nx < npad ? nx : npad - 1];
+  s.pn = nx < npad ? pv : (1u << 24);
+  s.g = f32x4{0.f, 0.f, 0.f, 0.f};
+}
+
+template <bool BWD>
+__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, const float* gv, WStage& s) {
+  if (!BWD) return;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = (int)(s.p[j] & 0xFFFFFFu);
+    s.g[j] = lds_bit(mask, c) ? gv[c] : 0.f;
+  }
+}
+
+template <bool BWD>
+__device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned long long* mask, const WStage& s,
+                                           int64_t k) {
+  const int lane = threadIdx.x & 63;
+  uint32_t adv[4];
+  double v[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    adv[j] = s.p[j] >> 24;
+    const int c = (int)(s.p[j] & 0xFFFFFFu);
+    v[j] = BWD ? (double)s.w[j] * (double)s.g[j] : (lds_bit(mask, c) ? (double)s.w[j] : 0.0);
+  }
+  // this lane's open segment and row-start count
+  int f = 0, cnt = 0;
+  double x = 0.0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (adv[j]) {
+      f = 1;
+      x = 0.0;
+    }
+    x += v[j];
+    cnt += (int)adv[j];
+  }
+  // wave scans: inclusive prefix of the counts, segmented inclusive scan of (f, x)
+  int ci = cnt, fi = f;
+  double xi = x;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int c2 = __shfl_up(ci, off);
+    const int f2 = __shfl_up(fi, off);
+    const double x2 = __shfl_up(xi, off);
+    if (lane >= off) {
+      ci += c2;
+      if (!fi) xi += x2;
+      fi |= f2;
+    }
+  }
+  int cex = ci - cnt;
+  double sx = __shfl_up(xi, 1);
+  int sf = __shfl_up(fi, 1);
+  if (lane == 0) {
+    sx = 0.0;
+    sf = 0;
+  }
+  const int64_t rowbase = a.G.chunk_row[k];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (adv[j]) {
+      sx = 0.0;
+      sf = 1;
+    }
+    sx += v[j];
+    cex += (int)adv[j];
+    const uint32_t anext = j < 3 ? adv[j + 1] : (s.pn >> 24);
+    if (anext) {  // the row of contact j ends here
+      if (sf) a.out[rowbase + cex - 1] = sx;
+      else a.first_piece[k] = sx;
+    }
+  }
+  if (lane == kWave - 1 && (s.pn >> 24) == 0) {  // the chunk's last row continues
+    if (sf) a.last_piece[k] = sx;
+    else a.first_piece[k] = sx;
+  }
+}
+
+// Persistent edge-parallel neighbour sum: out / first_piece / last_piece as
+// described above; forward values are the weights of infectious senders,
+// reverse values w * g for senders with a non-zero adjoint.
+template <bool BWD>
+__global__ void __launch_bounds__(kFastBlock) k_gather_fast(GatherArgs a) {
+  __shared__ unsigned long long mask[kFastMaskWords];
+  const int tid = threadIdx.x;
+  const DGraph& G = a.G;
+  const int words = (G.N + 63) >> 6;
+  for (int x = tid; x < words; x += kFastBlock) mask[x] = a.mask[x];
+  __syncthreads();
+  const int64_t nw = (int64_t)gridDim.x * (kFastBlock / kWave);
+  const int64_t gw = (int64_t)blockIdx.x * (kFastBlock / kWave) + (tid >> 6);
+  const int64_t nch = G.n_chunks;
+  if (gw >= nch) return;
+  const int64_t mine = (nch - 1 - gw) / nw + 1;
+  auto chunk = [&](int64_t q) { return gw + (q < mine ? q : mine - 1) * nw; };
+  // three register stages rotate by unrolling: the chunk being reduced, the
+  // next one (adjoint gathers in flight), the one after (contacts in flight)
+  auto body = [&](WStage& cur, WStage& nxt, WStage& far, int64_t q) {
+    wstage_load(G, far, chunk(q + 2));
+    wstage_gather<BWD>(mask, a.g, nxt);
+    wave_chunk<BWD>(a, mask, cur, chunk(q));
+  };
+  WStage s0, s1, s2;
+  wstage_load(G, s0, chunk(0));
+  wstage_load(G, s1, chunk(1));
+  wstage_gather<BWD>(mask, a.g, s0);
+  for (int64_t q = 0; q < mine; q += 3) {
+    body(s0, s1, s2, q);
+    if (q + 1 >= mine) break;
+    body(s1, s2, s0, q + 1);
+    if (q + 2 >= mine) break;
+    body(s2, s0, s1, q + 2);
+  }
+}
+
+// neighbour sum of receiver i from the gather outputs (pieces in chunk order)
+__device__ __forceinline__ double gathered(const DGraph& G, const GatherArgs& ga, int i) {
+  const int64_t e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
+  if (e0 == e1) return 0.0;
+  const int64_t kA = e0 >> kChunkShift, kB = (e1 - 1) >> kChunkShift;
+  if (kA == kB) return ga.out[i];
+  double s = ga.last_piece[kA];
+  for (int64_t k = kA + 1; k <= kB; ++k) s += ga.first_piece[k];
+  return s;
+}
+
+// ------------------------------------------------------------------ agent passes
+
+// Forward: A = neighbour sum (+ daily random layer), draw, progress, masks of
+// day t+1, counts.
+__global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, GatherArgs ga) {
+  __shared__ unsigned scnt[kCnt];
+  const int tid = threadIdx.x;
+  if (tid < kCnt) scnt[tid] = 0u;
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const int t = a.t;
+  // clear the masks of day t+2 (read last on day t-1, written next on day t+1)
+  for (int64_t x = blockIdx.x * (int64_t)kBlock + tid; x < a.mask_words; x += (int64_t)gridDim.x * kBlock)
+    a.mI_clr[x] = 0ull;
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + tid;
+  const bool on = i < G.N;
+  uint32_t newst = 0u;
+  bool removed = false;
+  if (on) {
+    double A = gathered(G, ga, i) * P.TI;
+    if (a.A_er) {
+      A += a.A_er[i];
+      a.A_er[i] = 0.0;
+    }
+    if (a.A_st) a.A_st[i] = (float)A;
+    const HardDay hd = hard_agent_day(P, a.rng, a.stream, t, 0, 0, (uint32_t)i, G.age[i], A, a.rec_in[i], nullptr);
+    if (a.fl_st) a.fl_st[i] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
+    newst = hd.newst;
+    removed = hd.removed;
+    a.rec_out[i] = hd.rec;
+  }
+  const int lane = tid & 63;
+  const unsigned long long bI = __ballot(on && newst == ST_I);
+  if (lane == 0) or_ballot(a.mI_next, blockIdx.x * kBlock + (tid & ~63), bI);
+  if (a.cnt) {
+    const unsigned long long c0 = __ballot(on && newst == ST_S), c1 = __ballot(on && newst == ST_E),
+                             c3 = __ballot(on && newst == ST_R), c4 = __ballot(on && newst == ST_M),
+                             c5 = __ballot(on && removed);
+    if (lane == 0) {
+      atomicAdd(&scnt[ST_S], (unsigned)__popcll(c0));
+      atomicAdd(&scnt[ST_E], (unsigned)__popcll(c1));
+      atomicAdd(&scnt[ST_I], (unsigned)__popcll(bI));
+      atomicAdd(&scnt[ST_R], (unsigned)__popcll(c3));
+      atomicAdd(&scnt[ST_M], (unsigned)__popcll(c4));
+      atomicAdd(&scnt[5], (unsigned)__popcll(c5));
+    }
+    __syncthreads();
+    if (tid < 6 && scnt[tid]) {
+      const int slot = blockIdx.x & (kSlots - 1);
+      atomicAdd(&a.cnt[(((int64_t)t) * kSlots + slot) * kCnt + tid], (double)scnt[tid]);
+    }
+  }
+}
+
+// Reverse step t: record inf_bar^t (+ daily random layer) in the window ring,
+// then the adjoint of day t-1 (t >= 1) or of the initial infections (t = 0);
+// g^{t-1} and its non-zero mask for the next step's gather.
+__global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, GatherArgs ga) {
+  __shared__ double sg[2 + 16];
+  const int tid = threadIdx.x;
+  if (tid < 18) sg[tid] = 0.0;
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const int t = a.t;
+  const int W = P.tau_E + P.tau_I;
+  for (int64_t x = blockIdx.x * (int64_t)kBlock + tid; x < fm.words; x += (int64_t)gridDim.x * kBlock)
+    fm.clr[x] = 0ull;
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + tid;
+  const bool on = i < G.N;
+  double g_new = 0.0;
+  const double m = P.m[0];
+  if (on) {
+    double infbar = 0.0;
+    if (a.do_gather) {
+      infbar = gathered(G, ga, i);
+      if (a.infbar_er) {
+        infbar += a.infbar_er[i];
+        a.infbar_er[i] = 0.0;
+      }
+      a.ring[(int64_t)(t % W) * G.N + i] = (float)infbar;
+    }
+    const int age = G.age[i];
+    const double Sbar1 = (double)a.Sbar[i];
+    if (t >= 1) {
+      const int d = t - 1;
+      double sE = 0.0, sI = 0.0;
+      for (int k = 1; k <= W; ++k) {
+        const double v = (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+        if (k <= P.tau_E) sE += v; else sI += v;
+      }
+      const double drm_bar = (d + W < P.K) ? m * a.Dbar[d + W] : 0.0;
+      const uint32_t fl = a.fl_st[i];
+      const double Aday = (double)a.A_st[i];
+      const AdjOut ad = agent_adjoint(P, a.rng, a.stream, d, 0, 0, (uint32_t)i, age, Aday, (double)(fl & 1u),
+                                      (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
+      a.Sbar[i] = (float)ad.Sbar;
+      a.g_prev[i] = (float)ad.g;
+      g_new = (double)(float)ad.g;
+      if (ad.lam_bar != 0.0) {
+        const double base = ad.lam_bar * Aday / (double)P.Z[0];
+        atomicAdd(&sg[0], base * (double)P.S[age]);
+        atomicAdd(&sg[2 + age], base * (double)P.R[d]);
+      }
+    } else {
+      double sI = 0.0;
+      for (int k = 0; k < P.tau_I; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
+      const double x0_bar = P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[P.tau_I - 1] : 0.0) - Sbar1;
+      const double u = unit_u(rng_block(a.rng, (uint32_t)i, kDayInit, TAG_INIT, 0u, a.stream).x);
+      double y0, dy0;
+      relaxed_init((double)P.i0[0], u, P.tau, y0, dy0);
+      const double v = x0_bar * dy0;
+      if (v != 0.0) atomicAdd(&sg[1], v);
+    }
+  }
+  const unsigned long long bz = __ballot(on && g_new != 0.0);
+  if ((tid & 63) == 0) or_ballot(fm.next, blockIdx.x * kBlock + (tid & ~63), bz);
+  __syncthreads();
+  const int slot = blockIdx.x & (kSlots - 1);
+  if (t >= 1) {
+    if (tid == 0 && sg[0] != 0.0) atomicAdd(&a.gR[((int64_t)(t - 1)) * kSlots + slot], sg[0]);
+    if (tid < P.n_age && sg[2 + tid] != 0.0) atomicAdd(&a.gS[((int64_t)tid) * kSlots + slot], sg[2 + tid]);
+  } else if (tid == 0 && sg[1] != 0.0) {
+    atomicAdd(&a.gi0[slot], sg[1]);
+  }
+}
+
+template __global__ void k_gather_fast<false>(GatherArgs);
+template __global__ void k_gather_fast<true>(GatherArgs);
+
+}  // namespace gabm

@@ -86,6 +86,14 @@ struct BwdArgs {
   double* gi0;         // [n_sets][kSlots]
 };
 
+// non-zero masks of the rate adjoint g for the persistent reverse kernel
+struct FastMasks {
+  const unsigned long long* cur;  // g^t
+  unsigned long long* next;       // g^{t-1}, written
+  unsigned long long* clr;        // cleared for step t-2
+  int64_t words;
+};
+
 struct FinArgs {
   int K, n_sets, soft, target_stride;
   const float* m;
@@ -119,6 +127,21 @@ template <typename RT, bool SOFT>
 __global__ void k_day_fwd(FwdArgs<RT> a);
 template <typename RT, bool SOFT>
 __global__ void k_day_bwd(BwdArgs<RT> a);
+// persistent neighbour sum over the fast tiles with an LDS-resident mask
+struct GatherArgs {
+  DGraph G;
+  const unsigned long long* mask;  // one bit per agent
+  const float* g;                  // reverse: rate adjoints (read where the bit is set)
+  double* out;                     // [N] sums of rows inside one chunk
+  double* first_piece;             // [n_chunks]
+  double* last_piece;              // [n_chunks]
+  double TI;
+};
+
+template <bool BWD>
+__global__ void k_gather_fast(GatherArgs a);
+__global__ void k_agent_fwd(FwdArgs<float> a, GatherArgs ga);
+__global__ void k_agent_bwd(BwdArgs<float> a, FastMasks fm, GatherArgs ga);
 __global__ void k_fin_fwd(FinArgs a);
 __global__ void k_dbar_eff(int n_out, int K, const double* Dbar, const double* w, const double* db, double* out);
 __global__ void k_fin_bwd(FinBwdArgs a);

@@ -8,6 +8,7 @@
 // A1-A6 of Appendix A (one-day steps; no transmission on the day of exposure;
 // no reinfection; contacts accumulate within a day, not across days) and the
 // Gumbel-softmax relaxation of Appendix B.
+#include "agent.h"
 #include "day_kernels.h"
 #include "tile.h"
 
@@ -231,13 +232,13 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
       p = pop_of_agent(G, i);
       const int set = set_of(P, p);
       const uint32_t loc = (uint32_t)(i - G.pop_off[p]);
-      const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + pre_age], Zp = P.Z[p];
-      const double lam = rate(Rt, Sa, A, Zp);
-      const double q = -expm1(-lam);
-      const double u = unit_u(rng_block(a.rng, loc, (uint32_t)t, TAG_INFECT, (uint32_t)p, a.stream).x);
-      if (a.lam_out) a.lam_out[i] = lam;
       if (a.A_st) a.A_st[i] = (RT)A;
       if (SOFT) {
+        const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + pre_age], Zp = P.Z[p];
+        const double lam = rate(Rt, Sa, A, Zp);
+        const double q = -expm1(-lam);
+        const double u = unit_u(rng_block(a.rng, loc, (uint32_t)t, TAG_INFECT, (uint32_t)p, a.stream).x);
+        if (a.lam_out) a.lam_out[i] = lam;
         double y, dydl;
         relaxed_sample(lam, q, u, P.tau, y, dydl);
         const double S0 = (double)a.Sv[i];
@@ -263,31 +264,11 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
         cS = S1; cE = wE; cI = wI; cRM = 1.0 - S1 - wE - wI;
         cD = old + (t == P.tau_I - 1 ? x0 : 0.0);
       } else {
-        const uint32_t r = pre_rec;
-        const uint32_t st = rec_stage(r);
-        uint32_t tm = rec_timer(r);
-        const bool h = u < q;
-        if (a.fl_st) a.fl_st[i] = (uint8_t)((st == ST_S ? 1u : 0u) | (h ? 2u : 0u));
-        uint32_t nr = r;
-        newst = st;
-        if (st == ST_E || st == ST_I) {
-          tm -= 1;
-          if (tm == 0) {
-            if (st == ST_E) {
-              newst = ST_I;
-              tm = (uint32_t)P.tau_I;
-            } else {
-              const double um = unit_u(rng_block(a.rng, loc, (uint32_t)t, TAG_MORT, (uint32_t)p, a.stream).x);
-              newst = um < (double)P.m[set] ? ST_M : ST_R;
-              removed = true;
-            }
-          }
-          nr = (r & 0xFFFF0000u) | (tm << 8) | newst;
-        } else if (st == ST_S && h) {
-          newst = ST_E;
-          nr = make_rec(ST_E, (uint32_t)P.tau_E, t);
-        }
-        a.rec_out[i] = nr;
+        const HardDay hd = hard_agent_day(P, a.rng, a.stream, t, set, p, loc, pre_age, A, pre_rec, a.lam_out ? &a.lam_out[i] : nullptr);
+        if (a.fl_st) a.fl_st[i] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
+        newst = hd.newst;
+        removed = hd.removed;
+        a.rec_out[i] = hd.rec;
       }
     }
     if (!SOFT) {
@@ -408,27 +389,21 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           if (k <= P.tau_E) sE += v; else sI += v;
         }
         const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + W] : 0.0;
-        const double Sbar1 = pre_Sbar;
-        const double xi_bar = drm_bar + P.TI * sI + P.TE * sE - Sbar1;
         const double A = pre_A;
-        const double Rt = P.R[set * P.K + d], Sa = P.S[set * P.n_age + pre_age], Zp = P.Z[p];
-        const double lam = rate(Rt, Sa, A, Zp);
-        const double q = -expm1(-lam);
-        const double u = unit_u(rng_block(a.rng, loc, (uint32_t)d, TAG_INFECT, (uint32_t)p, a.stream).x);
-        double y, dydl;
-        relaxed_sample(lam, q, u, P.tau, y, dydl);
         double Sv, h;
         if (SOFT) {
           Sv = (double)a.S_st[i];
-          h = y;
+          h = 0.0;
         } else {
-          const uint32_t fl = pre_fl;
-          Sv = (double)(fl & 1u);
-          h = (double)((fl >> 1) & 1u);
+          Sv = (double)(pre_fl & 1u);
+          h = (double)((pre_fl >> 1) & 1u);
         }
-        a.Sbar[i] = (RT)(Sbar1 + h * xi_bar);
-        const double lam_bar = Sv * xi_bar * dydl;
-        a.g_prev[i] = (RT)(Rt * Sa / Zp * lam_bar);
+        const AdjOut ad = agent_adjoint(P, a.rng, a.stream, d, set, p, loc, pre_age, A, Sv, h, SOFT, sE, sI, pre_Sbar,
+                                        drm_bar);
+        a.Sbar[i] = (RT)ad.Sbar;
+        const double lam_bar = ad.lam_bar;
+        a.g_prev[i] = (RT)ad.g;
+        const double Rt = P.R[set * P.K + d], Sa = P.S[set * P.n_age + pre_age], Zp = P.Z[p];
         if (lam_bar != 0.0) {
           const double base = lam_bar * A / Zp;
           if (o_tile >= 0) {

@@ -17,6 +17,15 @@ constexpr int kTileRows = 256;   // receivers per tile (one thread each in the e
 constexpr int kSlots = 64;       // spread of global FP64 accumulators (contention)
 constexpr int kCnt = 8;          // per-day aggregates: S,E,I,R,M snapshot counts, removals, spare x2
 constexpr uint32_t kDayInit = 0xFFFFFFFFu;
+// persistent kernels: one 1024-thread block per compute unit holding a
+// one-bit-per-agent mask in LDS
+constexpr int kFastBlock = 1024;
+constexpr int kFastCap = 4096;     // contacts per tile
+constexpr int kFastRows = 1024;    // receivers per tile
+constexpr int kFastMaskWords = 16384;  // 64-bit words of LDS mask: up to 2^20 agents
+// wave chunks of the edge-parallel neighbour sum: 64 lanes x 4 contacts
+constexpr int kChunk = 256;
+constexpr int kChunkShift = 8;
 
 enum : uint32_t { ST_S = 0, ST_E = 1, ST_I = 2, ST_R = 3, ST_M = 4 };
 enum : uint32_t { TAG_INIT = 0, TAG_INFECT = 1, TAG_MORT = 2, TAG_ER = 3 };
@@ -101,6 +110,14 @@ struct DGraph {
   const float* w;          // [E]
   const int32_t* tile_row; // [n_tiles+1]
   const TileInfo* tiles;   // [n_tiles]
+  const TileInfo* ftiles;  // [n_ftiles] tiles of the persistent kernels
+  int32_t n_ftiles;
+  // edge-parallel form: sender | (rows starting at this contact) << 24, padded
+  // with zero contacts to a multiple of kChunk; first row of each chunk
+  const uint32_t* colp;    // [n_chunks * kChunk]
+  const float* wp;         // [n_chunks * kChunk]
+  const int32_t* chunk_row;  // [n_chunks] rows that start before the chunk
+  int64_t n_chunks;
   const uint8_t* age;      // [N]
   const uint16_t* pop_of;  // [N]
   const int32_t* pop_off;  // [n_pops+1]
@@ -133,10 +150,10 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// sum over the block of 256 threads; every thread receives the result.
-// `scratch` holds at least kBlock/kWave values.
-template <typename T>
-__device__ __forceinline__ T block_sum(T v, T* scratch) {
+// sum over a block of NT threads; every thread receives the result.
+// `scratch` holds at least NT/kWave values.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum_n(T v, T* scratch) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   __syncthreads();
@@ -144,8 +161,13 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
   __syncthreads();
   T s = scratch[0];
 #pragma unroll
-  for (int k = 1; k < kBlock / kWave; ++k) s += scratch[k];
+  for (int k = 1; k < NT / kWave; ++k) s += scratch[k];
   return s;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T* scratch) {
+  return block_sum_n<kBlock>(v, scratch);
 }
 
 __device__ __forceinline__ int pop_of_agent(const DGraph& G, int i) { return G.n_pops == 1 ? 0 : (int)G.pop_of[i]; }

@@ -247,6 +247,32 @@ __global__ void k_check_sym(const int64_t* row_ptr, const int32_t* col, const fl
   }
 }
 
+// rows starting at each contact position (empty rows included; rows starting
+// at the end of the contact list are not counted)
+__global__ void k_row_starts(const int64_t* row_ptr, int32_t N, int64_t E, unsigned int* adv) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = row_ptr[r];
+    if (p < E) atomicAdd(&adv[p], 1u);
+  }
+}
+
+// packed sender | min(row starts, 255) << 24, zero padding up to n_pad; flag
+// when a count does not fit in 8 bits
+__global__ void k_pack_cols(const int32_t* col, const float* w, const unsigned int* adv, int64_t E, int64_t n_pad,
+                            uint32_t* colp, float* wp, uint32_t* flag) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_pad; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < E) {
+      const unsigned int a = adv[e];
+      if (a > 255u) atomicOr(flag, 1u);
+      colp[e] = (uint32_t)col[e] | (min(a, 255u) << 24);
+      wp[e] = w[e];
+    } else {
+      colp[e] = 0u;
+      wp[e] = 0.f;
+    }
+  }
+}
+
 __global__ void k_pop_of(const int32_t* pop_off, int n_pops, int32_t N, uint16_t* pop_of) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
     pop_of[i] = (uint16_t)pop_search(pop_off, n_pops, i);
@@ -262,9 +288,11 @@ __global__ void k_weight_sum(const float* w, int64_t E, double* out) {
 }
 
 void Graph::release() {
-  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(tiles); hipFree(age); hipFree(pop_of); hipFree(pop_off);
+  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(tiles); hipFree(ftiles); hipFree(colp); hipFree(wp); hipFree(chunk_row); hipFree(age); hipFree(pop_of); hipFree(pop_off);
   hipFree(er_off);
-  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; tiles = nullptr; age = nullptr; pop_of = nullptr;
+  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; tiles = nullptr; ftiles = nullptr; colp = nullptr; wp = nullptr; chunk_row = nullptr;
+  n_chunks = 0;
+  age = nullptr; pop_of = nullptr;
   pop_off = nullptr; er_off = nullptr;
 }
 
@@ -275,9 +303,10 @@ static int grid_for(int64_t n, int per = kBlock) {
   return (int)g;
 }
 
-// Greedy tiles of consecutive receivers: at most kTileRows rows and
-// kTileCap staged contacts; a row longer than kTileCap forms a tile alone.
-static void make_tiles(const std::vector<int64_t>& rp, std::vector<int32_t>& tiles, int32_t& n_long, int32_t& maxdeg) {
+// Greedy tiles of consecutive receivers: at most `rows` rows and `cap`
+// staged contacts; a row longer than `cap` forms a tile alone.
+static void make_tiles(const std::vector<int64_t>& rp, std::vector<int32_t>& tiles, int32_t& n_long, int32_t& maxdeg,
+                       int64_t cap = kTileCap, int32_t rows = kTileRows) {
   const int32_t N = (int32_t)rp.size() - 1;
   tiles.clear();
   tiles.push_back(0);
@@ -287,14 +316,14 @@ static void make_tiles(const std::vector<int64_t>& rp, std::vector<int32_t>& til
   while (r < N) {
     const int64_t d = rp[r + 1] - rp[r];
     maxdeg = std::max<int32_t>(maxdeg, (int32_t)d);
-    if (d > kTileCap) {
+    if (d > cap) {
       ++n_long;
       ++r;
       tiles.push_back(r);
       continue;
     }
     int32_t r1 = r + 1;
-    while (r1 < N && r1 - r < kTileRows && rp[r1 + 1] - rp[r] <= kTileCap) {
+    while (r1 < N && r1 - r < rows && rp[r1 + 1] - rp[r] <= cap) {
       maxdeg = std::max<int32_t>(maxdeg, (int32_t)(rp[r1 + 1] - rp[r1]));
       ++r1;
     }
@@ -434,6 +463,65 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
   }
   GABM_HIP(dalloc(&G.tiles, tinfo.size()));
   GABM_HIP(hipMemcpyAsync(G.tiles, tinfo.data(), sizeof(TileInfo) * tinfo.size(), hipMemcpyHostToDevice, st));
+  {
+    std::vector<int32_t> ft;
+    int32_t nl = 0, md = 0;
+    make_tiles(rp, ft, nl, md, kFastCap, kFastRows);
+    G.n_ftiles = (int32_t)ft.size() - 1;
+    std::vector<TileInfo> fi(G.n_ftiles);
+    for (int32_t k = 0; k < G.n_ftiles; ++k) {
+      fi[k].r0 = ft[k];
+      fi[k].r1 = ft[k + 1];
+      fi[k].e0 = rp[ft[k]];
+      fi[k].e1 = rp[ft[k + 1]];
+      fi[k].pad0 = fi[k].pad1 = 0;
+    }
+    GABM_HIP(dalloc(&G.ftiles, fi.size()));
+    GABM_HIP(hipMemcpyAsync(G.ftiles, fi.data(), sizeof(TileInfo) * fi.size(), hipMemcpyHostToDevice, st));
+    GABM_HIP(hipStreamSynchronize(st));
+  }
+  // edge-parallel form for the persistent kernels (senders below 2^24)
+  if (E > 0 && N < (1 << 24)) {
+    const int64_t nch = (E + kChunk - 1) / kChunk;
+    const int64_t npad = nch * kChunk;
+    unsigned int* adv = nullptr;
+    uint32_t* oflag = nullptr;
+    GABM_HIP(dalloc(&adv, E));
+    GABM_HIP(dalloc(&oflag, 1));
+    GABM_HIP(hipMemsetAsync(adv, 0, sizeof(unsigned int) * E, st));
+    GABM_HIP(hipMemsetAsync(oflag, 0, sizeof(uint32_t), st));
+    GABM_HIP(dalloc(&G.colp, npad));
+    GABM_HIP(dalloc(&G.wp, npad));
+    hipLaunchKernelGGL(k_row_starts, dim3(grid_for(N)), dim3(kBlock), 0, st, G.row_ptr, N, E, adv);
+    hipLaunchKernelGGL(k_pack_cols, dim3(grid_for(npad)), dim3(kBlock), 0, st, G.col, G.w, adv, E, npad, G.colp,
+                       G.wp, oflag);
+    std::vector<int32_t> crow(nch);
+    {
+      int64_t r = 0;  // rows r with rp[r] < k * kChunk
+      for (int64_t k = 0; k < nch; ++k) {
+        const int64_t e0 = k * kChunk;
+        while (r <= N && rp[r] < e0) ++r;
+        crow[k] = (int32_t)r;
+      }
+    }
+    GABM_HIP(dalloc(&G.chunk_row, nch));
+    GABM_HIP(hipMemcpyAsync(G.chunk_row, crow.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, st));
+    uint32_t of = 0;
+    GABM_HIP(hipMemcpyAsync(&of, oflag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    GABM_HIP(hipStreamSynchronize(st));
+    hipFree(adv);
+    hipFree(oflag);
+    if (of) {  // more than 255 consecutive empty rows somewhere: keep the tile kernels only
+      hipFree(G.colp);
+      hipFree(G.wp);
+      hipFree(G.chunk_row);
+      G.colp = nullptr;
+      G.wp = nullptr;
+      G.chunk_row = nullptr;
+    } else {
+      G.n_chunks = nch;
+    }
+  }
   GABM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
   GABM_HIP(hipMemcpyAsync(&G.weight_sum, wsum, sizeof(double), hipMemcpyDeviceToHost, st));
   GABM_HIP(hipStreamSynchronize(st));

@@ -5,6 +5,7 @@
 // automatic differentiation of the unrolled loop would do, Appendix B).
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "batched.h"
 #include "day_kernels.h"
@@ -84,7 +85,7 @@ void Sim::release() {
   bwd_graphs.clear();
   void* ps[] = {rec[0], rec[1], maskI[0], maskI[1], maskI[2], maskE[0], maskE[1], maskE[2], A_er, Sv, x0, xi_ring,
                 inf[0], inf[1], A_st, fl_st, S_st, ck_rec, ck_soft, cnt, cnt0, drm, Dbar, Dbar_eff, ring, Sbar, g[0], g[1],
-                infbar_er, gR, gS, gi0};
+                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece};
   for (void* p : ps) hipFree(p);
 }
 
@@ -147,6 +148,18 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
   s.precision = run->precision;
   s.use_graph = run->use_hip_graph;
   s.time_kernels = run->time_kernels;
+  s.schedule = run->schedule;
+  {
+    int dev = 0, ncu = 0;
+    hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
+    s.n_cu = ncu;
+  }
+  const bool fast_shape = s.schedule == 0 && s.n_cu > 0 && s.B == 1 && !s.per_pop && G.n_pops == 1 && G.n_chunks > 0 &&
+                          (int64_t)G.N <= (int64_t)kFastMaskWords * 64 && run->precision == GABM_F32 &&
+                          s.mode != GABM_SOFT;
+  s.fast_fwd_ok = fast_shape;
+  s.fast_bwd_ok = fast_shape && s.mode == GABM_HARD_ST;
   s.rsz = run->precision == GABM_F64 ? 8 : 4;
   s.NB = (int64_t)G.N * s.B;
   if (s.B == 1) {
@@ -218,6 +231,12 @@ gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc
   AL(s.gR, L.gR);
   AL(s.gS, L.gS);
   AL(s.gi0, L.gi0);
+  if (s.fast_bwd_ok)
+    for (int k = 0; k < 3; ++k) AL(s.gz[k], (size_t)s.mask_words * 8);
+  if (s.fast_fwd_ok || s.fast_bwd_ok) {
+    AL(s.Abuf, (size_t)G.N * 8);
+    AL(s.piece, (size_t)G.n_chunks * 2 * 8);
+  }
 #undef AL
   return GABM_OK;
 }
@@ -309,7 +328,13 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.cnt = count ? s.cnt : nullptr;
   a.lam_out = nullptr;
   KTime kt(s, st, true);
-  if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+  if (std::is_same<RT, float>::value && s.fast_fwd_ok && !withE) {
+    GatherArgs ga;
+    ga.G = dg; ga.mask = s.maskI[t % 3]; ga.g = nullptr; ga.out = s.Abuf; ga.TI = P.TI;
+    ga.first_piece = s.piece; ga.last_piece = s.piece + dg.n_chunks;
+    hipLaunchKernelGGL(k_gather_fast<false>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
+    hipLaunchKernelGGL(k_agent_fwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a, ga);
+  } else if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_day_fwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   s.cur = 1 - s.cur;
 }
@@ -385,7 +410,18 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.S_st = (t >= 1 && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.Dbar = s.Dbar_eff; a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
   KTime kt(s, st, false);
-  if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+  if (std::is_same<RT, float>::value && s.fast_bwd_ok) {
+    FastMasks fm;
+    fm.cur = s.gz[t % 3];
+    fm.next = s.gz[(t + 2) % 3];
+    fm.clr = s.gz[(t + 1) % 3];
+    fm.words = s.mask_words;
+    GatherArgs ga;
+    ga.G = dg; ga.mask = s.gz[t % 3]; ga.g = (const float*)s.g[t & 1]; ga.out = s.Abuf; ga.TI = 1.0;
+    ga.first_piece = s.piece; ga.last_piece = s.piece + dg.n_chunks;
+    if (gather) hipLaunchKernelGGL(k_gather_fast<true>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
+    hipLaunchKernelGGL(k_agent_bwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm, ga);
+  } else if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   else hipLaunchKernelGGL((k_day_bwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
 }
 
@@ -404,6 +440,7 @@ static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st
   fill0(s.ring, (size_t)s.W * s.NB * s.rsz, st);
   fill0(s.Sbar, s.NB * s.rsz, st);
   fill0(s.infbar_er, s.infbar_er ? (size_t)s.NB * 8 : 0, st);
+  for (int k = 0; k < 3; ++k) fill0(s.gz[k], s.gz[k] ? (size_t)s.mask_words * 8 : 0, st);
   fill0(s.gR, (size_t)s.n_sets * s.K * kSlots * 8, st);
   fill0(s.gS, (size_t)s.n_sets * s.n_age * kSlots * 8, st);
   fill0(s.gi0, (size_t)s.n_sets * kSlots * 8, st);

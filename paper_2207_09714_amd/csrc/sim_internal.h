@@ -62,6 +62,15 @@ struct Sim {
   size_t ev_used = 0;
   hipEvent_t next_event();
 
+  // persistent kernels (float state, one parameter set, one population, up to
+  // 2^20 agents): eligibility and the non-zero masks of the rate adjoint
+  int n_cu = 0;
+  int schedule = 0;  // 0 auto, 1 tile kernels only
+  bool fast_fwd_ok = false, fast_bwd_ok = false;
+  unsigned long long* gz[3] = {nullptr, nullptr, nullptr};
+  double* Abuf = nullptr;  // [N] neighbour sums handed from the gather to the agent pass
+  double* piece = nullptr; // [2 * n_chunks] sums of rows crossing chunk boundaries
+
   int next_day = 0;     // forward progress for gabm_day_fwd
   int next_bwd = -1;    // reverse progress for gabm_day_bwd
   bool fwd_done = false;

@@ -94,8 +94,8 @@ __device__ __forceinline__ void tile_pass(const DGraph& G, const TileBounds& tb,
   const int g = tid / tpr, k = tid & (tpr - 1);
   double acc = 0.0;
   if (g < nr) {
-    const int s = sh.rofs[g], len = sh.rofs[g + 1] - s;
-    for (int j = k; j < len; j += tpr) acc += sh.val[s + j];
+    const int s = sh.rofs[g], en = min(sh.rofs[g + 1], kTileCap);
+    for (int j = s + k; j < en; j += tpr) acc += sh.val[j];
   }
   for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
   if (g < nr && k == 0) sh.row[g] = acc;

@@ -203,7 +203,7 @@ class Simulator:
 
     def __init__(self, graph: Graph, *, n_sets=1, K, Z, tau_E=3, tau_I=5, mode=HARD_ST, n_reps=1,
                  per_pop_params=False, ckpt_every=0, precision=F32, use_hip_graph=False, T=(0, 0, 1, 0, 0),
-                 tau_g=0.5, time_kernels=False):
+                 tau_g=0.5, time_kernels=False, schedule=0):
         self.graph = graph
         self.n_sets, self.K, self.n_reps = int(n_sets), int(K), int(n_reps)
         self.per_pop = bool(per_pop_params)
@@ -216,7 +216,8 @@ class Simulator:
                          zeros[:n_sets] + 0.5)
         run = L.RunDesc()
         run.n_reps, run.ckpt_every, run.precision, run.use_hip_graph, run.schedule, run.time_kernels = (
-            int(n_reps), int(ckpt_every), int(precision), 1 if use_hip_graph else 0, 0, 1 if time_kernels else 0)
+            int(n_reps), int(ckpt_every), int(precision), 1 if use_hip_graph else 0, int(schedule),
+            1 if time_kernels else 0)
         self._run = run
         h = C.c_void_p()
         check(lib().gabm_sim_create(graph.handle, C.byref(pb.c), C.byref(run), C.byref(h)))

@@ -42,13 +42,13 @@ def graph_of(G, wl, **kw):
 
 
 def run_gpu(G, wl, *, mode=None, precision=0, ckpt=0, target=None, hip_graph=False, backward=False, T=None,
-            R=None, graph=None, reps=1):
+            R=None, graph=None, reps=1, schedule=0):
     mode = wl.mode if mode is None else mode
     g = graph if graph is not None else graph_of(G, wl)
     per_pop = wl.per_pop_params
     sim = G.Simulator(g, n_sets=wl.n_sets, K=wl.K, Z=wl.Z, mode=mode, ckpt_every=ckpt, precision=precision,
                       use_hip_graph=hip_graph, T=wl.T if T is None else T, tau_g=wl.tau_g, per_pop_params=per_pop,
-                      n_reps=reps)
+                      n_reps=reps, schedule=schedule)
     pb = sim.params(wl.R if R is None else R, wl.S, wl.m, wl.i0)
     out = sim.forward(pb, seed=wl.seed, target=None if target is None else torch.tensor(target, device="cuda"))
     res = {k: v.cpu().numpy().copy() for k, v in out.items()}
@@ -241,6 +241,23 @@ def test_forward_trajectory_bit_exact(G, O, name, wkw, rkw):
     assert np.array_equal(st, ref["stage"][-1])
 
 
+@pytest.mark.parametrize("name,wkw", [("c3", dict(n_agents=40000, K=30)), ("c2", dict(n_agents=6000, K=20))])
+def test_persistent_and_tile_kernels_agree(G, O, name, wkw):
+    """The persistent LDS-mask kernels and the receiver-tile kernels give the
+    same trajectory (bit-exact) and the same gradients."""
+    wl = make_workload(name, **wkw)
+    tgt = np.linspace(0.0, 1.0, wl.K)
+    _say(f"persistent vs tile {name} {wkw}")
+    fast = run_gpu(G, wl, mode=1, ckpt=6, target=tgt, backward=True, schedule=0)
+    tile = run_gpu(G, wl, mode=1, ckpt=6, target=tgt, backward=True, schedule=1)
+    assert np.array_equal(fast["counts"], tile["counts"]) and np.array_equal(fast["records"], tile["records"])
+    for k in ("dR", "dS", "dm", "di0"):
+        assert np.allclose(fast[k], tile[k], rtol=1e-6, atol=1e-9 * np.abs(tile[k]).max()), k
+    ref = O.run_workload(wl, mode=O.HARD_ST, target=tgt, directions=O.standard_directions(wl.K, 8))
+    assert np.array_equal(fast["counts"][0], ref["counts"])
+    assert_grads(grad_vector(fast), ref["dL"])
+
+
 def test_long_rows_and_edge_cases(G, O):
     _say("long rows / edge cases")
     # a hub with 6000 contacts (longer than one tile) plus a household layer
@@ -256,12 +273,13 @@ def test_long_rows_and_edge_cases(G, O):
     g = G.Graph(n_agents=n, src=src, dst=dst, w=w, age=age)
     assert g.info()["n_long_rows"] >= 1
     K = 15
-    sim = G.Simulator(g, K=K, Z=Z, mode=G.HARD_ST)
-    pb = sim.params(np.full(K, 3.0, np.float32), S, [0.05], [0.05])
-    out = sim.forward(pb, seed=3)
     ref = O.run(age=age, pop_offsets=[0, n], src=src, dst=dst, w=w, K=K, R=3.0, S=S, m=0.05, i0=0.05, Z=Z,
                 mode=O.HARD_ST, seed=3)
-    assert np.array_equal(out["counts"][0].cpu().numpy(), ref["counts"])
+    for sched in (0, 1):
+        sim = G.Simulator(g, K=K, Z=Z, mode=G.HARD_ST, schedule=sched)
+        pb = sim.params(np.full(K, 3.0, np.float32), S, [0.05], [0.05])
+        out = sim.forward(pb, seed=3)
+        assert np.array_equal(out["counts"][0].cpu().numpy(), ref["counts"]), sched
     # a single agent with no contacts; and everyone infected
     g1 = G.Graph(n_agents=1, src=np.zeros(0, np.int32), dst=np.zeros(0, np.int32), age=[3])
     s1 = G.Simulator(g1, K=3, Z=[1.0], mode=G.PLAIN)
