@@ -31,7 +31,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("day_kernels.hip", "tile.h", "gabm_device.h", "day_kernels.h", "batched.hip")
+KERNEL_SOURCES = ("day_kernels.hip", "day_fast.hip", "agent.h", "tile.h", "gabm_device.h", "day_kernels.h",
+                  "graph_build.hip", "batched.hip")
+
+
+# kernel class -> device function name as rocprofv3 reports it
+KERNEL_NAMES = {
+    "gather_fwd": "k_gather_fast<false>", "agent_fwd": "k_agent_fwd", "day_fwd": "k_day_fwd",
+    "gather_bwd": "k_gather_fast<true>", "agent_bwd": "k_agent_bwd", "day_bwd": "k_day_bwd", "er": "k_er",
+}
 
 
 def kernel_source_hash() -> str:
@@ -55,7 +63,8 @@ def load_target(name, K):
 def read_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on different kernel sources."""
-    fn = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.txt")
+    tag = kernel.replace("<", "_").replace(">", "").replace("false", "fwd").replace("true", "bwd")
+    fn = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}.txt")
     if not os.path.exists(fn):
         return None
     kv = {}
@@ -71,22 +80,37 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
-def alg_bytes(kind: str, N: int, E: int, W: int, store_frac: float, has_er: bool) -> float:
-    """Algorithmic HBM bytes of one fused day launch (B = 1, float32 store).
+def alg_bytes(kind: str, N: int, E: int, W: int, store_frac: float, has_er: bool) -> float | None:
+    """Algorithmic HBM bytes of one launch of a day kernel (one simulation,
+    float32 state and store).
 
-    Forward: col 4 + w 4 per contact; per agent row_ptr 8 + record read 4 and
-    write 4 + age 1, plus A 4 + flags 1 when the day is stored for the reverse
-    pass.  Reverse: col 4 + w 4 per contact; per agent row_ptr 8 + ring write
-    4 and read 4W + adjoint S r/w 8 + stored A 4 + flags 1 + age 1 + g 4.
-    The infectiousness bit mask (N/8 bytes) and the gathered adjoint g (4N)
-    are cache-resident and not counted per contact."""
-    if kind == "fwd":
-        b = 8.0 * E + 17.0 * N + 5.0 * N * store_frac
-    else:
-        b = 8.0 * E + (30.0 + 4.0 * W) * N
-    if has_er:
-        b += 16.0 * N
-    return b
+    gather_fwd / gather_bwd (persistent neighbour sum): packed sender 4 +
+    weight 4 per contact; the one-bit-per-agent mask N/8 read once; one
+    double per receiver and, per 256-contact chunk, two boundary pieces and the
+    chunk's first row (20 bytes).  The reverse pass also reads the rate
+    adjoint g of senders whose mask bit is set: random, cache-served, not
+    counted.
+    agent_fwd: row_ptr 8, neighbour sum 8, age 1, record read 4 + write 4,
+    next-day mask and cleared mask N/8 each; stored A 4 + flags 1 on stored
+    days; random-layer sum read 8 + clear 8.
+    agent_bwd: row_ptr 8, neighbour sum 8, window ring write 4 + read 4W,
+    adjoint S read 4 + write 4, stored A 4 + flags 1, age 1, g write 4, the two
+    mask words N/8 each; random-layer adjoint read 8 + clear 8.
+    day_fwd / day_bwd (fused tiled kernels): contacts 8 per contact plus the
+    per-agent bytes of the agent kernels without the neighbour sum."""
+    chunks = (E + 255) // 256
+    er = 16.0 * N if has_er else 0.0
+    if kind in ("gather_fwd", "gather_bwd"):
+        return 8.0 * E + N / 8.0 + 8.0 * N + 20.0 * chunks
+    if kind == "agent_fwd":
+        return 25.0 * N + N / 4.0 + 5.0 * N * store_frac + er
+    if kind == "agent_bwd":
+        return (38.0 + 4.0 * W) * N + N / 4.0 + er
+    if kind == "day_fwd":
+        return 8.0 * E + 17.0 * N + N / 4.0 + 5.0 * N * store_frac + er
+    if kind == "day_bwd":
+        return 8.0 * E + (30.0 + 4.0 * W) * N + N / 4.0 + er
+    return None
 
 
 def cpu_baseline(wl, days: int):
@@ -232,29 +256,33 @@ def main():
         "graph_gen_s": gen_s,
     }
     kt = res["kt"]
-    if kt is not None and kt["fwd_launches"] > 0 and kt["bwd_launches"] > 0:
-        # first pass: K launches (the last segment stored); replay: every other segment again, stored
+    if kt is not None and any(v["launches"] for v in kt.values()):
+        # first pass: K forward days (the last segment stored); the reverse
+        # pass replays every other segment, stored
         n_seg = (K + ck - 1) // ck if ck else 1
-        fwd_launches_per_step = K + (n_seg - 1) * ck
-        fwd_b = alg_bytes("fwd", N, E - 2 * info["er_pairs_per_day"], W, K / fwd_launches_per_step, has_er)
-        bwd_b = alg_bytes("bwd", N, E - 2 * info["er_pairs_per_day"], W, 1.0, has_er)
-        f_avg = kt["fwd_ms"] / kt["fwd_launches"] * 1e-3
-        b_avg = kt["bwd_ms"] / kt["bwd_launches"] * 1e-3
-        dom = "fwd" if kt["fwd_ms"] >= kt["bwd_ms"] else "bwd"
-        ab, dur = (fwd_b, f_avg) if dom == "fwd" else (bwd_b, b_avg)
-        kname = "k_day_fwd" if dom == "fwd" else "k_day_bwd"
-        achieved = ab / dur / 1e9
-        traffic = read_traffic(kname, wl.name)
+        store_frac = K / (K + (n_seg - 1) * ck)
+        E_graph = E - 2 * info["er_pairs_per_day"]
+        kernels = {}
+        for name, v in kt.items():
+            if not v["launches"]:
+                continue
+            avg = v["ms"] / v["launches"] * 1e-3
+            ab = alg_bytes(name, N, E_graph, W, store_frac, has_er)
+            kernels[name] = {"launches_per_step": v["launches"] / args.steps, "avg_ms": avg * 1e3,
+                             "ms_per_step": v["ms"] / args.steps,
+                             "alg_bytes_per_launch": ab, "alg_GBps": None if ab is None else ab / avg / 1e9}
+        timed_ms = sum(v["ms"] for v in kt.values()) / args.steps
+        kernels["share_of_step"] = timed_ms / (res["diff_s"] * 1e3)
+        out["kernels"] = kernels
+        dom = max((k for k in kernels if k != "share_of_step" and kernels[k]["alg_bytes_per_launch"] is not None),
+                  key=lambda k: kernels[k]["ms_per_step"])
+        d = kernels[dom]
+        kname = KERNEL_NAMES[dom]
+        achieved = d["alg_GBps"]
         out["roofline"] = {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "alg_bytes_per_launch": ab, "avg_launch_ms": dur * 1e3}
-        out["kernels"] = {
-            "k_day_fwd": {"launches_per_step": kt["fwd_launches"] / args.steps, "avg_ms": f_avg * 1e3,
-                          "alg_GBps": fwd_b / f_avg / 1e9},
-            "k_day_bwd": {"launches_per_step": kt["bwd_launches"] / args.steps, "avg_ms": b_avg * 1e3,
-                          "alg_GBps": bwd_b / b_avg / 1e9},
-            "share_of_step": (kt["fwd_ms"] + kt["bwd_ms"]) / args.steps / (res["diff_s"] * 1e3),
-        }
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": read_traffic(kname, wl.name),
+                           "alg_bytes_per_launch": d["alg_bytes_per_launch"], "avg_launch_ms": d["avg_ms"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_days)
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "

@@ -285,15 +285,31 @@ gabm_status gabm_day_bwd(gabm_sim s, const gabm_params *p, const gabm_rng *rng, 
  * agent-major: record of simulation b of agent i at i*B + b), for tests. */
 gabm_status gabm_sim_records(gabm_sim s, const gabm_rec **rec);
 
-/* Durations of the fused day kernels launched since the last reset, from
- * the HIP events recorded on their launch stream when the simulation was
- * created with time_kernels = 1 and use_hip_graph = 0.  Synchronises with the
- * recorded events.  reset != 0 clears the record. */
+/* Durations of the day kernels launched since the last reset, per kernel
+ * class, from a pair of HIP events recorded around each launch on its launch
+ * stream when the simulation was created with time_kernels = 1 and
+ * use_hip_graph = 0.  Synchronises with the recorded events.  reset != 0
+ * clears the record.  Classes:
+ *   GABM_KT_GATHER_FWD  persistent neighbour sum of the forward day
+ *   GABM_KT_AGENT_FWD   per-agent forward day (draw, progress, masks, counts)
+ *   GABM_KT_DAY_FWD     fused tiled forward day (when the split path is not used)
+ *   GABM_KT_GATHER_BWD  persistent neighbour sum of the reverse step
+ *   GABM_KT_AGENT_BWD   per-agent reverse step (window ring, adjoint, grads)
+ *   GABM_KT_DAY_BWD     fused tiled reverse step
+ *   GABM_KT_ER          daily random layer (forward or reverse)          */
+enum {
+  GABM_KT_GATHER_FWD = 0,
+  GABM_KT_AGENT_FWD = 1,
+  GABM_KT_DAY_FWD = 2,
+  GABM_KT_GATHER_BWD = 3,
+  GABM_KT_AGENT_BWD = 4,
+  GABM_KT_DAY_BWD = 5,
+  GABM_KT_ER = 6,
+  GABM_KT_N = 7
+};
 typedef struct {
-  double fwd_ms;         /* total of forward-day kernel durations */
-  int64_t fwd_launches;
-  double bwd_ms;         /* total of reverse-day kernel durations */
-  int64_t bwd_launches;
+  double ms[GABM_KT_N];        /* total duration per class */
+  int64_t launches[GABM_KT_N]; /* launches per class */
 } gabm_kernel_times;
 
 gabm_status gabm_sim_kernel_times(gabm_sim s, gabm_kernel_times *out, int32_t reset);

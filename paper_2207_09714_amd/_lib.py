@@ -64,9 +64,11 @@ class RunDesc(C.Structure):
                 ("use_hip_graph", C.c_int32), ("schedule", C.c_int32), ("time_kernels", C.c_int32)]
 
 
+KT_CLASSES = ("gather_fwd", "agent_fwd", "day_fwd", "gather_bwd", "agent_bwd", "day_bwd", "er")
+
+
 class KernelTimes(C.Structure):
-    _fields_ = [("fwd_ms", C.c_double), ("fwd_launches", C.c_int64), ("bwd_ms", C.c_double),
-                ("bwd_launches", C.c_int64)]
+    _fields_ = [("ms", C.c_double * len(KT_CLASSES)), ("launches", C.c_int64 * len(KT_CLASSES))]
 
 
 class FwdOut(C.Structure):

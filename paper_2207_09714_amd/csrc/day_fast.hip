@@ -40,34 +40,44 @@ __device__ __forceinline__ uint32_t lds_bit(const unsigned long long* m, int c) 
 // agent pass.  Waves are independent: no block barrier after the mask load.
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// software pipeline of the persistent gather (kGatherAhead <= kStages - 2)
+constexpr int kStages = 3;
+constexpr int kGatherAhead = 1;
+static_assert(kGatherAhead >= 1 && kGatherAhead <= kStages - 2, "pipeline depth");
+// fourth word of a raw buffer descriptor on gfx9-family chips (gfx950)
+constexpr int kBufferWord3 = 0x00020000;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct WStage {
   u32x4 p;   // packed senders of this lane's 4 contacts
   f32x4 w;
-  uint32_t pn;  // packed sender of the following contact (an artificial row start after the list)
+  uint32_t hdr; // chunk header: rows starting before the chunk | next-chunk row start << 31
   f32x4 g;   // reverse: adjoints of the senders whose mask bit is set, else 0
 };
 
 __device__ __forceinline__ void wstage_load(const DGraph& G, WStage& s, int64_t k) {
   const int lane = threadIdx.x & 63;
   const int64_t base = k * kChunk + lane * 4;
-  const int64_t npad = G.n_chunks * kChunk;
   s.p = __builtin_nontemporal_load((const u32x4*)(G.colp + base));
   s.w = __builtin_nontemporal_load((const f32x4*)(G.wp + base));
-  const int64_t nx = base + 4;
-  const uint32_t pv = G.colp[nx < npad ? nx : npad - 1];
-  s.pn = nx < npad ? pv : (1u << 24);
+  s.hdr = G.chunk_row[k];
   s.g = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
+// Reverse: g of the senders whose mask bit is set.  The load is a raw buffer
+// load whose offset is moved past the end of the buffer for a clear bit; the
+// hardware returns 0 for such a lane without a memory request, so there is no
+// branch around the load (a branch would make the compiler wait for it at
+// once).
 template <bool BWD>
-__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, const float* gv, WStage& s) {
+__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, __amdgpu_buffer_rsrc_t gbuf,
+                                              WStage& s) {
   if (!BWD) return;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int c = (int)(s.p[j] & 0xFFFFFFu);
-    s.g[j] = lds_bit(mask, c) ? gv[c] : 0.f;
+    const uint32_t c = s.p[j] & 0xFFFFFFu;
+    const uint32_t off = lds_bit(mask, (int)c) ? c * 4u : 0x80000000u;
+    s.g[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(gbuf, off, 0, 0));
   }
 }
 
@@ -84,39 +94,36 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
     v[j] = BWD ? (double)s.w[j] * (double)s.g[j] : (lds_bit(mask, c) ? (double)s.w[j] : 0.0);
   }
   // this lane's open segment and row-start count
-  int f = 0, cnt = 0;
+  int cnt = 0;
   double x = 0.0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    if (adv[j]) {
-      f = 1;
-      x = 0.0;
-    }
+    if (adv[j]) x = 0.0;
     x += v[j];
     cnt += (int)adv[j];
   }
-  // wave scans: inclusive prefix of the counts, segmented inclusive scan of (f, x)
-  int ci = cnt, fi = f;
+  // wave scans: inclusive prefix of the counts and segmented inclusive scan
+  // of x; a window of lanes holds a row start exactly when its count is
+  // non-zero, so the segment flag needs no scan of its own
+  int ci = cnt;
   double xi = x;
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     const int c2 = __shfl_up(ci, off);
-    const int f2 = __shfl_up(fi, off);
     const double x2 = __shfl_up(xi, off);
     if (lane >= off) {
+      if (ci == 0) xi += x2;
       ci += c2;
-      if (!fi) xi += x2;
-      fi |= f2;
     }
   }
   int cex = ci - cnt;
   double sx = __shfl_up(xi, 1);
-  int sf = __shfl_up(fi, 1);
-  if (lane == 0) {
-    sx = 0.0;
-    sf = 0;
-  }
-  const int64_t rowbase = a.G.chunk_row[k];
+  int sf = cex > 0;
+  if (lane == 0) sx = 0.0;
+  // does a row start at the contact after this lane's last one?
+  const uint32_t a_next = __shfl_down(adv[0], 1);
+  const uint32_t after = lane == kWave - 1 ? (s.hdr >> 31) : a_next;
+  const int64_t rowbase = (int64_t)(s.hdr & 0x7FFFFFFFu);
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (adv[j]) {
@@ -125,13 +132,13 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
     }
     sx += v[j];
     cex += (int)adv[j];
-    const uint32_t anext = j < 3 ? adv[j + 1] : (s.pn >> 24);
+    const uint32_t anext = j < 3 ? adv[j + 1] : after;
     if (anext) {  // the row of contact j ends here
       if (sf) a.out[rowbase + cex - 1] = sx;
       else a.first_piece[k] = sx;
     }
   }
-  if (lane == kWave - 1 && (s.pn >> 24) == 0) {  // the chunk's last row continues
+  if (lane == kWave - 1 && after == 0) {  // the chunk's last row continues
     if (sf) a.last_piece[k] = sx;
     else a.first_piece[k] = sx;
   }
@@ -152,25 +159,27 @@ __global__ void __launch_bounds__(kFastBlock) k_gather_fast(GatherArgs a) {
   const int64_t gw = (int64_t)blockIdx.x * (kFastBlock / kWave) + (tid >> 6);
   const int64_t nch = G.n_chunks;
   if (gw >= nch) return;
+  // raw buffer over g (N floats): offsets at or past N * 4 read as 0
+  const __amdgpu_buffer_rsrc_t gbuf =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.g, (short)0, BWD ? G.N * 4 : 0, kBufferWord3);
   const int64_t mine = (nch - 1 - gw) / nw + 1;
   auto chunk = [&](int64_t q) { return gw + (q < mine ? q : mine - 1) * nw; };
-  // three register stages rotate by unrolling: the chunk being reduced, the
-  // next one (adjoint gathers in flight), the one after (contacts in flight)
-  auto body = [&](WStage& cur, WStage& nxt, WStage& far, int64_t q) {
-    wstage_load(G, far, chunk(q + 2));
-    wstage_gather<BWD>(mask, a.g, nxt);
-    wave_chunk<BWD>(a, mask, cur, chunk(q));
-  };
-  WStage s0, s1, s2;
-  wstage_load(G, s0, chunk(0));
-  wstage_load(G, s1, chunk(1));
-  wstage_gather<BWD>(mask, a.g, s0);
-  for (int64_t q = 0; q < mine; q += 3) {
-    body(s0, s1, s2, q);
-    if (q + 1 >= mine) break;
-    body(s1, s2, s0, q + 1);
-    if (q + 2 >= mine) break;
-    body(s2, s0, s1, q + 2);
+  // kStages register stages rotate by unrolling: chunk c is reduced in step
+  // c, its contacts were requested kStages - 1 steps earlier and (reverse)
+  // its adjoints kGatherAhead steps earlier
+  WStage st[kStages];
+#pragma unroll
+  for (int j = 0; j < kStages - 1; ++j) wstage_load(G, st[j], chunk(j));
+#pragma unroll
+  for (int j = 0; j < kGatherAhead; ++j) wstage_gather<BWD>(mask, gbuf, st[j]);
+  for (int64_t q = 0; q < mine; q += kStages) {
+#pragma unroll
+    for (int j = 0; j < kStages; ++j) {
+      if (q + j >= mine) break;
+      wstage_load(G, st[(j + kStages - 1) % kStages], chunk(q + j + kStages - 1));
+      wstage_gather<BWD>(mask, gbuf, st[(j + kGatherAhead) % kStages]);
+      wave_chunk<BWD>(a, mask, st[j], chunk(q + j));
+    }
   }
 }
 

@@ -116,7 +116,8 @@ struct DGraph {
   // with zero contacts to a multiple of kChunk; first row of each chunk
   const uint32_t* colp;    // [n_chunks * kChunk]
   const float* wp;         // [n_chunks * kChunk]
-  const int32_t* chunk_row;  // [n_chunks] rows that start before the chunk
+  // per chunk: rows that start before it | (a row starts right after it) << 31
+  const uint32_t* chunk_row;  // [n_chunks]
   int64_t n_chunks;
   const uint8_t* age;      // [N]
   const uint16_t* pop_of;  // [N]

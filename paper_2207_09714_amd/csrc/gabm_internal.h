@@ -38,7 +38,7 @@ struct Graph {
   int32_t n_ftiles = 0;
   uint32_t* colp = nullptr;
   float* wp = nullptr;
-  int32_t* chunk_row = nullptr;
+  uint32_t* chunk_row = nullptr;
   int64_t n_chunks = 0;  // 0 = edge-parallel form not available
   uint8_t* age = nullptr;
   uint16_t* pop_of = nullptr;

@@ -495,17 +495,28 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
     hipLaunchKernelGGL(k_row_starts, dim3(grid_for(N)), dim3(kBlock), 0, st, G.row_ptr, N, E, adv);
     hipLaunchKernelGGL(k_pack_cols, dim3(grid_for(npad)), dim3(kBlock), 0, st, G.col, G.w, adv, E, npad, G.colp,
                        G.wp, oflag);
-    std::vector<int32_t> crow(nch);
+    // per chunk: rows starting before it, and in bit 31 whether a row starts
+    // at the contact after it (always set for the last chunk, whose padding
+    // ends the list)
+    std::vector<uint32_t> crow(nch);
     {
       int64_t r = 0;  // rows r with rp[r] < k * kChunk
       for (int64_t k = 0; k < nch; ++k) {
         const int64_t e0 = k * kChunk;
         while (r <= N && rp[r] < e0) ++r;
-        crow[k] = (int32_t)r;
+        crow[k] = (uint32_t)r;
+      }
+      for (int64_t k = 0; k < nch; ++k) {  // crow[k + 1] is still unflagged here
+        bool starts = true;
+        if (k + 1 < nch) {
+          const int64_t rn = crow[k + 1];  // first row starting at or after the next chunk
+          starts = rn < N && rp[rn] == (k + 1) * kChunk;
+        }
+        if (starts) crow[k] |= 0x80000000u;
       }
     }
     GABM_HIP(dalloc(&G.chunk_row, nch));
-    GABM_HIP(hipMemcpyAsync(G.chunk_row, crow.data(), sizeof(int32_t) * nch, hipMemcpyHostToDevice, st));
+    GABM_HIP(hipMemcpyAsync(G.chunk_row, crow.data(), sizeof(uint32_t) * nch, hipMemcpyHostToDevice, st));
     uint32_t of = 0;
     GABM_HIP(hipMemcpyAsync(&of, oflag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));
     GABM_HIP(hipStreamSynchronize(st));

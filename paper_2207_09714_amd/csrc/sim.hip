@@ -28,13 +28,13 @@ hipEvent_t Sim::next_event() {
   return ev_pool[ev_used++];
 }
 
-// brackets a launch with a pair of events when kernel timing is on
+// brackets one launch with a pair of events when kernel timing is on
 struct KTime {
   Sim& s;
   hipStream_t st;
-  std::vector<std::pair<int, int>>* list;
+  int cls;
   int a = -1;
-  KTime(Sim& s_, hipStream_t st_, bool fwd) : s(s_), st(st_), list(fwd ? &s_.ev_fwd : &s_.ev_bwd) {
+  KTime(Sim& s_, hipStream_t st_, int cls_) : s(s_), st(st_), cls(cls_) {
     if (!s.time_kernels || s.use_graph) return;
     hipEvent_t e = s.next_event();
     if (!e) return;
@@ -46,31 +46,24 @@ struct KTime {
     hipEvent_t e = s.next_event();
     if (!e) return;
     hipEventRecord(e, st);
-    list->emplace_back(a, (int)s.ev_used - 1);
+    s.ev_k[cls].emplace_back(a, (int)s.ev_used - 1);
   }
 };
 
 gabm_status sim_kernel_times(Sim& s, gabm_kernel_times* out, int reset) {
-  double f = 0.0, b = 0.0;
-  for (auto& pr : s.ev_fwd) {
-    float ms = 0.f;
-    GABM_HIP(hipEventSynchronize(s.ev_pool[pr.second]));
-    GABM_HIP(hipEventElapsedTime(&ms, s.ev_pool[pr.first], s.ev_pool[pr.second]));
-    f += ms;
+  for (int c = 0; c < GABM_KT_N; ++c) {
+    double tot = 0.0;
+    for (auto& pr : s.ev_k[c]) {
+      float ms = 0.f;
+      GABM_HIP(hipEventSynchronize(s.ev_pool[pr.second]));
+      GABM_HIP(hipEventElapsedTime(&ms, s.ev_pool[pr.first], s.ev_pool[pr.second]));
+      tot += ms;
+    }
+    out->ms[c] = tot;
+    out->launches[c] = (int64_t)s.ev_k[c].size();
   }
-  for (auto& pr : s.ev_bwd) {
-    float ms = 0.f;
-    GABM_HIP(hipEventSynchronize(s.ev_pool[pr.second]));
-    GABM_HIP(hipEventElapsedTime(&ms, s.ev_pool[pr.first], s.ev_pool[pr.second]));
-    b += ms;
-  }
-  out->fwd_ms = f;
-  out->fwd_launches = (int64_t)s.ev_fwd.size();
-  out->bwd_ms = b;
-  out->bwd_launches = (int64_t)s.ev_bwd.size();
   if (reset) {
-    s.ev_fwd.clear();
-    s.ev_bwd.clear();
+    for (auto& v : s.ev_k) v.clear();
     s.ev_used = 0;
   }
   return GABM_OK;
@@ -303,6 +296,7 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     ErArgs e;
     e.G = dg; e.rng = rng; e.stream = stream; e.t = t; e.TE = P.TE; e.TI = P.TI; e.acc = s.A_er;
     const int nb = blocks_capped(dg.er_total);
+    KTime ke(s, st, GABM_KT_ER);
     if (soft) hipLaunchKernelGGL(k_er_vec<RT>, dim3(nb), dim3(kBlock), 0, st, e, (const RT*)s.inf[s.cur]);
     else hipLaunchKernelGGL(k_er_fwd_hard, dim3(nb), dim3(kBlock), 0, st, e, (const uint32_t*)s.maskI[t % 3],
                             withE ? (const uint32_t*)s.maskE[t % 3] : nullptr);
@@ -327,15 +321,21 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.S_st = (store && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.cnt = count ? s.cnt : nullptr;
   a.lam_out = nullptr;
-  KTime kt(s, st, true);
   if (std::is_same<RT, float>::value && s.fast_fwd_ok && !withE) {
     GatherArgs ga;
     ga.G = dg; ga.mask = s.maskI[t % 3]; ga.g = nullptr; ga.out = s.Abuf; ga.TI = P.TI;
     ga.first_piece = s.piece; ga.last_piece = s.piece + dg.n_chunks;
-    hipLaunchKernelGGL(k_gather_fast<false>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
+    {
+      KTime kt(s, st, GABM_KT_GATHER_FWD);
+      hipLaunchKernelGGL(k_gather_fast<false>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
+    }
+    KTime kt(s, st, GABM_KT_AGENT_FWD);
     hipLaunchKernelGGL(k_agent_fwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a, ga);
-  } else if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_day_fwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+  } else {
+    KTime kt(s, st, GABM_KT_DAY_FWD);
+    if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_day_fwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+  }
   s.cur = 1 - s.cur;
 }
 
@@ -397,6 +397,7 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   if (gather && has_er) {
     ErArgs e;
     e.G = dg; e.rng = rng; e.stream = stream; e.t = t; e.TE = P.TE; e.TI = P.TI; e.acc = s.infbar_er;
+    KTime ke(s, st, GABM_KT_ER);
     hipLaunchKernelGGL(k_er_vec<RT>, dim3(blocks_capped(dg.er_total)), dim3(kBlock), 0, st, e, (const RT*)s.g[t & 1]);
   }
   BwdArgs<RT> a;
@@ -409,7 +410,6 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.fl_st = (t >= 1 && !soft) ? s.fl_st + (int64_t)slot * s.NB : nullptr;
   a.S_st = (t >= 1 && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.Dbar = s.Dbar_eff; a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
-  KTime kt(s, st, false);
   if (std::is_same<RT, float>::value && s.fast_bwd_ok) {
     FastMasks fm;
     fm.cur = s.gz[t % 3];
@@ -419,10 +419,17 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     GatherArgs ga;
     ga.G = dg; ga.mask = s.gz[t % 3]; ga.g = (const float*)s.g[t & 1]; ga.out = s.Abuf; ga.TI = 1.0;
     ga.first_piece = s.piece; ga.last_piece = s.piece + dg.n_chunks;
-    if (gather) hipLaunchKernelGGL(k_gather_fast<true>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
+    if (gather) {
+      KTime kt(s, st, GABM_KT_GATHER_BWD);
+      hipLaunchKernelGGL(k_gather_fast<true>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
+    }
+    KTime kt(s, st, GABM_KT_AGENT_BWD);
     hipLaunchKernelGGL(k_agent_bwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm, ga);
-  } else if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
-  else hipLaunchKernelGGL((k_day_bwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+  } else {
+    KTime kt(s, st, GABM_KT_DAY_BWD);
+    if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_day_bwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+  }
 }
 
 static void fin_bwd(Sim& s, const gabm_grads* out, hipStream_t st) {

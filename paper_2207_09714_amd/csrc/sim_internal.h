@@ -58,7 +58,7 @@ struct Sim {
   // kernel timing: event pairs around each fused day kernel
   int32_t time_kernels = 0;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, int>> ev_fwd, ev_bwd;  // indices into ev_pool
+  std::vector<std::pair<int, int>> ev_k[GABM_KT_N];  // per kernel class: indices into ev_pool
   size_t ev_used = 0;
   hipEvent_t next_event();
 

@@ -298,7 +298,7 @@ class Simulator:
     def kernel_times(self, reset=True) -> dict:
         kt = L.KernelTimes()
         check(lib().gabm_sim_kernel_times(self.handle, C.byref(kt), 1 if reset else 0))
-        return {k: getattr(kt, k) for k, _ in L.KernelTimes._fields_}
+        return {name: {"ms": kt.ms[c], "launches": int(kt.launches[c])} for c, name in enumerate(L.KT_CLASSES)}
 
     def records(self) -> torch.Tensor:
         p = C.c_void_p()
