@@ -80,6 +80,71 @@ def read_traffic(kernel: str, workload: str):
         return None
 
 
+def _pmc_per_dispatch(d: str, counter: str):
+    """{kernel name: mean counter value per dispatch} from one rocprofv3 --pmc CSV run."""
+    import csv
+    import glob
+
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no counter_collection.csv under {d}")
+    acc = {}
+    for row in csv.DictReader(open(files[0])):
+        if row.get("Counter_Name") != counter:
+            continue
+        name = row["Kernel_Name"]
+        did = row.get("Dispatch_Id", "")
+        acc.setdefault(name, {}).setdefault(did, 0.0)
+        acc[name][did] += float(row["Counter_Value"])
+    return {k: sum(v.values()) / len(v) for k, v in acc.items()}
+
+
+def traffic_from_pmc(root: str, workload: str, commands: dict) -> list[str]:
+    """Write profiles/traffic_<kernel>_<workload>.txt for the split day kernels
+    from four rocprofv3 --pmc runs under `root`: fetch/ and write/ (FETCH_SIZE,
+    WRITE_SIZE of `bench.py --only diff`) and copy_fetch/, copy_write/ (the
+    same counters on `bench.py --only copy`, a copy of known size).  Each
+    counter is scaled by (known copy bytes) / (copy kernel's counter bytes)."""
+    n_copy = 256 * 1024 * 1024  # bytes read and written by the copy leg
+    cf = _pmc_per_dispatch(os.path.join(root, "copy_fetch"), "FETCH_SIZE")
+    cw = _pmc_per_dispatch(os.path.join(root, "copy_write"), "WRITE_SIZE")
+    # the copy kernel is the one that both reads and writes the most
+    ck = max((k for k in cf if k in cw), key=lambda k: min(cf[k], cw[k]))
+    f_fetch = n_copy / (cf[ck] * 1024.0)
+    f_write = n_copy / (cw[ck] * 1024.0)
+    kf = _pmc_per_dispatch(os.path.join(root, "fetch"), "FETCH_SIZE")
+    kw = _pmc_per_dispatch(os.path.join(root, "write"), "WRITE_SIZE")
+    written = []
+    sha = kernel_source_hash()
+    for cls, kname in KERNEL_NAMES.items():
+        full = [k for k in kf if k.split("(")[0].replace("void ", "").replace("gabm::", "").strip() == kname]
+        if not full or full[0] not in kw:
+            continue
+        k = full[0]
+        fetch_b = kf[k] * 1024.0 * f_fetch
+        write_b = kw[k] * 1024.0 * f_write
+        tag = kname.replace("<", "_").replace(">", "").replace("false", "fwd").replace("true", "bwd")
+        fn = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}.txt")
+        with open(fn, "w") as fh:
+            fh.write(f"# HBM traffic per launch of {kname} on workload {workload} (rocprofv3 --pmc)\n")
+            for what, cmd in commands.items():
+                fh.write(f"# {what}: {cmd}\n")
+            fh.write(f"# copy calibration: copy kernel {ck.split('(')[0][:80]!r} moved {n_copy} B each way;\n")
+            fh.write(f"#   FETCH_SIZE read {cf[ck]:.0f} KiB -> factor {f_fetch:.4f}, "
+                     f"WRITE_SIZE read {cw[ck]:.0f} KiB -> factor {f_write:.4f}\n")
+            fh.write(f"kernel = {kname}\n")
+            fh.write(f"fetch_kib_per_launch = {kf[k]:.1f}\n")
+            fh.write(f"write_kib_per_launch = {kw[k]:.1f}\n")
+            fh.write(f"fetch_factor = {f_fetch:.4f}\n")
+            fh.write(f"write_factor = {f_write:.4f}\n")
+            fh.write(f"hbm_read_bytes_per_launch = {fetch_b:.0f}\n")
+            fh.write(f"hbm_write_bytes_per_launch = {write_b:.0f}\n")
+            fh.write(f"hbm_bytes_per_launch = {fetch_b + write_b:.0f}\n")
+            fh.write(f"kernel_source_sha = {sha}\n")
+        written.append(fn)
+    return written
+
+
 def alg_bytes(kind: str, N: int, E: int, W: int, store_frac: float, has_er: bool) -> float | None:
     """Algorithmic HBM bytes of one launch of a day kernel (one simulation,
     float32 state and store).
@@ -145,10 +210,26 @@ def main():
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="eager launches with HIP-event kernel timing, or the day loop captured in hipGraphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-days", type=int, default=8)
+    ap.add_argument("--cpu-days", type=int, default=30)
     ap.add_argument("--only", choices=["diff", "plain", "copy"], default=None,
                     help="run a single leg (for profiler runs)")
+    ap.add_argument("--traffic-from", default=None, metavar="DIR",
+                    help="no run: turn the rocprofv3 --pmc runs under DIR (fetch/ write/ copy_fetch/ copy_write/) "
+                         "into profiles/traffic_<kernel>_<workload>.txt")
     args = ap.parse_args()
+
+    if args.traffic_from:
+        pmc = "timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 bench.py {a}"
+        cmds = {
+            "fetch": pmc.format(c="FETCH_SIZE", d=f"{args.traffic_from}/fetch", a="--only diff --steps 1 --warmup 0 --no-cpu-baseline"),
+            "write": pmc.format(c="WRITE_SIZE", d=f"{args.traffic_from}/write", a="--only diff --steps 1 --warmup 0 --no-cpu-baseline"),
+            "copy fetch": pmc.format(c="FETCH_SIZE", d=f"{args.traffic_from}/copy_fetch", a="--only copy"),
+            "copy write": pmc.format(c="WRITE_SIZE", d=f"{args.traffic_from}/copy_write", a="--only copy"),
+            "summary": f"python bench.py --traffic-from {args.traffic_from} --workload {args.workload}",
+        }
+        for fn in traffic_from_pmc(args.traffic_from, args.workload, cmds):
+            print(fn)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
