@@ -1,30 +1,453 @@
-// Batched simulations sharing one contact graph (placeholder: the entry
-// points reject B > 1 until the lane-per-simulation kernels land).
+// Batched day kernels: B simulations sharing one contact graph, one launch
+// per day for all of them (layout and lane mapping: batched.h).
+//
+// Forward day (Section 3.1, Eq. 1-3, Progress, Aggregate): for receiver i and
+// simulation b, A_ib = T_I * sum of w_ji over senders j infectious in b
+// (+ T_E * the same over exposed senders), formed in double precision in
+// contact order; then the draw, progress, the records and bit masks of day
+// t+1 and the daily counts -- all in the lanes that formed the sums.
+// Reverse step t (Appendix B; the adjoint of the same sum is a gather over the
+// same receiver-sorted CSR because every contact is listed both ways):
+// inf_bar^t_ib = sum of w_ij g^t_jb, recorded in the window ring, then the
+// agent adjoint of day t-1 (or of the initial draw at t = 0) and the
+// parameter-gradient partials.
+//
+// Work distribution: receiver tiles (at most kBTileCap contacts and
+// kBTileRows receivers, a longer row alone) are taken from a per-launch
+// counter by one lane group at a time.  Senders inactive in every simulation
+// (not infectious in the forward, zero adjoint in the reverse) are skipped by
+// a one-bit-per-agent mask held in LDS; the per-simulation loads of active
+// senders are raw buffer loads whose offset is pushed out of range for
+// skipped contacts, so the hardware returns 0 without a memory request.
+#include "agent.h"
 #include "batched.h"
 
 namespace gabm {
 
-template <typename RT>
-void batched_init(Sim&, const DParams&, Rng, hipStream_t) {}
-template <typename RT>
-void batched_day_fwd(Sim&, const DParams&, Rng, int, int, bool, hipStream_t) {}
-void batched_fin_fwd(Sim&, const DParams&, const double*, int, const gabm_fwd_out*, hipStream_t) {}
-template <typename RT>
-void batched_day_bwd(Sim&, const DParams&, Rng, int, int, hipStream_t) {}
-template <typename RT>
-void batched_forward(Sim&, const DParams&, Rng, const double*, int, const gabm_fwd_out*, hipStream_t) {}
-template <typename RT>
-void batched_backward(Sim&, const DParams&, Rng, const gabm_grads*, hipStream_t) {}
+namespace {
 
-template void batched_init<float>(Sim&, const DParams&, Rng, hipStream_t);
-template void batched_init<double>(Sim&, const DParams&, Rng, hipStream_t);
-template void batched_day_fwd<float>(Sim&, const DParams&, Rng, int, int, bool, hipStream_t);
-template void batched_day_fwd<double>(Sim&, const DParams&, Rng, int, int, bool, hipStream_t);
-template void batched_day_bwd<float>(Sim&, const DParams&, Rng, int, int, hipStream_t);
-template void batched_day_bwd<double>(Sim&, const DParams&, Rng, int, int, hipStream_t);
-template void batched_forward<float>(Sim&, const DParams&, Rng, const double*, int, const gabm_fwd_out*, hipStream_t);
-template void batched_forward<double>(Sim&, const DParams&, Rng, const double*, int, const gabm_fwd_out*, hipStream_t);
-template void batched_backward<float>(Sim&, const DParams&, Rng, const gabm_grads*, hipStream_t);
-template void batched_backward<double>(Sim&, const DParams&, Rng, const gabm_grads*, hipStream_t);
+constexpr int kRsrcWord3 = 0x00020000;   // fourth word of a raw buffer descriptor (gfx9 family)
+constexpr uint32_t kOut = 0x80000000u;   // an offset past every buffer: reads as 0
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void* p, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, p ? (int)bytes : 0, kRsrcWord3);
+}
+__device__ __forceinline__ uint32_t rload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+// the simulations of one lane
+template <int SPL>
+struct Slots {
+  int b[SPL];
+  bool ok[SPL];
+  int set[SPL];
+  uint32_t strm[SPL];
+  uint32_t widx[SPL];
+  uint32_t bsh[SPL];
+};
+
+template <int SPL>
+__device__ __forceinline__ Slots<SPL> lane_slots(const BSims& S, int gl) {
+  Slots<SPL> o;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    const int b = gl + S.LB * s;
+    o.ok[s] = b < S.B;
+    const int bb = o.ok[s] ? b : 0;
+    o.b[s] = bb;
+    o.set[s] = bb % S.n_sets;
+    o.strm[s] = S.stream0 + (uint32_t)(S.indep ? bb : bb / S.n_sets);
+    o.widx[s] = (uint32_t)bb >> 5;
+    o.bsh[s] = (uint32_t)bb & 31u;
+  }
+  return o;
+}
+
+// this group's bits of a wave ballot (bit k = lane k of the group)
+__device__ __forceinline__ unsigned long long group_bits(unsigned long long bal, int gq, int LB) {
+  return LB == 64 ? bal : (bal >> (gq * LB)) & ((1ull << LB) - 1ull);
+}
+
+// the group leader writes agent r's mask words from the ballots of its lanes
+template <int SPL>
+__device__ __forceinline__ void put_bits(uint32_t* m, int64_t r, const BSims& S, int gl, int gq,
+                                         const unsigned long long (&bal)[SPL]) {
+  if (m == nullptr || gl != 0) return;
+  uint32_t* row = m + r * S.bw;
+  if (S.LB == 64) {
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      if (2 * s < S.bw) row[2 * s] = (uint32_t)bal[s];
+      if (2 * s + 1 < S.bw) row[2 * s + 1] = (uint32_t)(bal[s] >> 32);
+    }
+  } else {
+    row[0] = (uint32_t)group_bits(bal[0], gq, S.LB);
+  }
+}
+
+template <int SPL>
+__device__ __forceinline__ bool group_any(const unsigned long long (&bal)[SPL], int gq, int LB) {
+  unsigned long long x = 0ull;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) x |= group_bits(bal[s], gq, LB);
+  return x != 0ull;
+}
+
+template <bool LDS>
+__device__ __forceinline__ bool any_bit(const unsigned long long* s_any, const unsigned long long* g_any, uint32_t c) {
+  const unsigned long long w = LDS ? s_any[c >> 6] : g_any[c >> 6];
+  return ((w >> (c & 63u)) & 1ull) != 0ull;
+}
+
+// next tile of this lane group (broadcast from the group leader)
+__device__ __forceinline__ int next_tile(unsigned int* work, int gl, int gq, int LB) {
+  int tile = 0;
+  if (gl == 0) tile = (int)atomicAdd(work, 1u);
+  return __shfl(tile, gq * LB);
+}
+
+}  // namespace
+
+// ----------------------------------------------------------------- initial infections
+// One lane group per agent: the INIT draw of every simulation (Bernoulli(i0)
+// of its set, entering I with a full timer), the day-0 masks and counts.
+template <int SPL>
+__global__ void __launch_bounds__(kBBlock) k_binit(BInitArgs a) {
+  __shared__ double s_c[kBMaxB * 2];
+  const int tid = threadIdx.x;
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const BSims& S = a.S;
+  for (int x = tid; x < S.B * 2; x += kBBlock) s_c[x] = 0.0;
+  __syncthreads();
+  const int LB = S.LB, lane = tid & 63, gl = lane & (LB - 1), gq = lane / LB;
+  const Slots<SPL> sl = lane_slots<SPL>(S, gl);
+  double cS[SPL], cI[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) cS[s] = cI[s] = 0.0;
+  const int64_t per_block = kBBlock / LB;
+  const int64_t ng = (int64_t)gridDim.x * per_block;
+  for (int64_t i = blockIdx.x * per_block + tid / LB; i < G.N; i += ng) {
+    const int p = pop_of_agent(G, (int)i);
+    const uint32_t loc = (uint32_t)(i - G.pop_off[p]);
+    unsigned long long bI[SPL], bE[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      bool inf = false;
+      if (sl.ok[s]) {
+        const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, sl.strm[s]).x);
+        inf = u < (double)P.i0[sl.set[s]];
+        a.rec[i * S.B + sl.b[s]] = inf ? make_rec(ST_I, (uint32_t)P.tau_I, -1) : make_rec(ST_S, 0, -1);
+        if (inf) cI[s] += 1.0; else cS[s] += 1.0;
+      }
+      bI[s] = __ballot(sl.ok[s] && inf);
+      bE[s] = 0ull;
+    }
+    put_bits<SPL>(a.mI, i, S, gl, gq, bI);
+    put_bits<SPL>(a.mE, i, S, gl, gq, bE);
+    if (gl == 0 && group_any<SPL>(bI, gq, LB)) atomicOr(&a.any[i >> 6], 1ull << (i & 63));
+  }
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+    if (sl.ok[s]) {
+      if (cS[s] != 0.0) atomicAdd(&s_c[sl.b[s] * 2], cS[s]);
+      if (cI[s] != 0.0) atomicAdd(&s_c[sl.b[s] * 2 + 1], cI[s]);
+    }
+  __syncthreads();
+  const int slot = blockIdx.x & (kSlots - 1);
+  for (int x = tid; x < S.B * 2; x += kBBlock) {
+    const double v = s_c[x];
+    if (v != 0.0) atomicAdd(&a.cnt0[((int64_t)(x >> 1) * kSlots + slot) * kCnt + ((x & 1) ? ST_I : ST_S)], v);
+  }
+}
+
+// masks of the current day rebuilt from the records (checkpoint restore)
+template <int SPL>
+__global__ void __launch_bounds__(kBBlock) k_bmask(BMaskArgs a) {
+  const int tid = threadIdx.x;
+  const BSims& S = a.S;
+  const int LB = S.LB, lane = tid & 63, gl = lane & (LB - 1), gq = lane / LB;
+  const Slots<SPL> sl = lane_slots<SPL>(S, gl);
+  const int64_t per_block = kBBlock / LB;
+  const int64_t ng = (int64_t)gridDim.x * per_block;
+  for (int64_t i = blockIdx.x * per_block + tid / LB; i < a.G.N; i += ng) {
+    unsigned long long bI[SPL], bE[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      const uint32_t st = sl.ok[s] ? rec_stage(a.rec[i * S.B + sl.b[s]]) : ST_S;
+      bI[s] = __ballot(sl.ok[s] && st == ST_I);
+      bE[s] = __ballot(sl.ok[s] && st == ST_E);
+    }
+    put_bits<SPL>(a.mI, i, S, gl, gq, bI);
+    put_bits<SPL>(a.mE, i, S, gl, gq, bE);
+    const bool act = group_any<SPL>(bI, gq, LB) || (a.mE != nullptr && group_any<SPL>(bE, gq, LB));
+    if (gl == 0 && act) atomicOr(&a.any[i >> 6], 1ull << (i & 63));
+  }
+}
+
+// ----------------------------------------------------------------- forward day
+template <int SPL, bool ANY_LDS>
+__global__ void __launch_bounds__(kBBlock) k_bfwd(BFwdArgs a) {
+  extern __shared__ unsigned long long lds[];
+  unsigned long long* s_any = lds;
+  unsigned int* s_cnt = (unsigned int*)(lds + (ANY_LDS ? a.any_words : 0));
+  const int tid = threadIdx.x;
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const BSims& S = a.S;
+  for (int x = tid; x < S.B * 6; x += kBBlock) s_cnt[x] = 0u;
+  if (ANY_LDS)
+    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.any_cur[x];
+  // the 'any' words of day t+2 (read last on day t-1, OR-ed next on day t+1)
+  for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
+    a.any_clr[x] = 0ull;
+  __syncthreads();
+  const int LB = S.LB, lane = tid & 63, gl = lane & (LB - 1), gq = lane / LB;
+  const Slots<SPL> sl = lane_slots<SPL>(S, gl);
+  const bool withE = a.mE != nullptr;
+  const int64_t mbytes = (int64_t)G.N * S.bw * 4;
+  const __amdgpu_buffer_rsrc_t rI = rsrc(a.mI, mbytes);
+  const __amdgpu_buffer_rsrc_t rE = rsrc(a.mE, mbytes);
+  unsigned int cnt[SPL][6];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) cnt[s][c] = 0u;
+
+  for (;;) {
+    const int tile = next_tile(a.work, gl, gq, LB);
+    if (tile >= G.n_btiles) break;
+    const TileInfo ti = G.btiles[tile];
+    int64_t e = ti.e0;
+    int64_t e_next = G.row_ptr[ti.r0 + 1];
+    for (int r = ti.r0; r < ti.r1; ++r) {
+      const int64_t e1 = e_next;
+      if (r + 1 < ti.r1) e_next = G.row_ptr[r + 2];
+      double aI[SPL], aE[SPL];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) aI[s] = aE[s] = 0.0;
+      for (; e < e1; e += kBUnroll) {
+        uint32_t c[kBUnroll];
+        float w[kBUnroll];
+#pragma unroll
+        for (int k = 0; k < kBUnroll; ++k) {
+          const int64_t pos = e + k < e1 ? e + k : e1 - 1;
+          c[k] = (uint32_t)G.col[pos];
+          w[k] = G.w[pos];
+        }
+        uint32_t vi[kBUnroll][SPL], ve[kBUnroll][SPL];
+#pragma unroll
+        for (int k = 0; k < kBUnroll; ++k) {
+          const bool need = (e + k < e1) && any_bit<ANY_LDS>(s_any, a.any_cur, c[k]);
+#pragma unroll
+          for (int s = 0; s < SPL; ++s) {
+            const uint32_t off = need ? (c[k] * (uint32_t)S.bw + sl.widx[s]) * 4u : kOut;
+            vi[k][s] = rload(rI, off);
+            ve[k][s] = withE ? rload(rE, off) : 0u;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kBUnroll; ++k)
+#pragma unroll
+          for (int s = 0; s < SPL; ++s) {
+            if ((vi[k][s] >> sl.bsh[s]) & 1u) aI[s] += (double)w[k];
+            if ((ve[k][s] >> sl.bsh[s]) & 1u) aE[s] += (double)w[k];
+          }
+      }
+      e = e1;
+      // the day of agent r in every simulation of this group
+      const int p = pop_of_agent(G, r);
+      const uint32_t loc = (uint32_t)(r - G.pop_off[p]);
+      const int age = G.age[r];
+      unsigned long long bI[SPL], bE[SPL];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        uint32_t newst = ST_S;
+        if (sl.ok[s]) {
+          const int64_t idx = (int64_t)r * S.B + sl.b[s];
+          const double A = P.TI * aI[s] + (withE ? P.TE * aE[s] : 0.0);
+          const HardDay hd =
+              hard_agent_day(P, a.rng, sl.strm[s], a.t, sl.set[s], p, loc, age, A, a.rec_in[idx], nullptr);
+          a.rec_out[idx] = hd.rec;
+          if (a.A_st) a.A_st[idx] = (float)A;
+          if (a.fl_st) a.fl_st[idx] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
+          newst = hd.newst;
+          cnt[s][newst] += 1u;
+          if (hd.removed) cnt[s][5] += 1u;
+        }
+        bI[s] = __ballot(sl.ok[s] && newst == ST_I);
+        bE[s] = __ballot(sl.ok[s] && newst == ST_E);
+      }
+      put_bits<SPL>(a.mI_next, r, S, gl, gq, bI);
+      if (withE) put_bits<SPL>(a.mE_next, r, S, gl, gq, bE);
+      const bool act = group_any<SPL>(bI, gq, LB) || (withE && group_any<SPL>(bE, gq, LB));
+      if (gl == 0 && act) atomicOr(&a.any_next[r >> 6], 1ull << (r & 63));
+    }
+  }
+  if (a.cnt == nullptr) return;
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+    if (sl.ok[s])
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (cnt[s][c]) atomicAdd(&s_cnt[sl.b[s] * 6 + c], cnt[s][c]);
+  __syncthreads();
+  const int slot = blockIdx.x & (kSlots - 1);
+  for (int x = tid; x < S.B * 6; x += kBBlock) {
+    const unsigned int v = s_cnt[x];
+    if (v) atomicAdd(&a.cnt[(((int64_t)(x / 6) * P.K + a.t) * kSlots + slot) * kCnt + x % 6], (double)v);
+  }
+}
+
+// ----------------------------------------------------------------- reverse step
+template <int SPL, bool ANY_LDS>
+__global__ void __launch_bounds__(kBBlock) k_bbwd(BBwdArgs a) {
+  extern __shared__ unsigned long long lds[];
+  const int tid = threadIdx.x;
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const BSims& S = a.S;
+  unsigned long long* s_any = lds;
+  double* s_gS = (double*)(lds + (ANY_LDS ? a.any_words : 0));  // [B][n_age] sum of lam_bar * A / Z
+  double* s_gi0 = s_gS + (int64_t)S.B * P.n_age;                 // [B]
+  for (int x = tid; x < S.B * (P.n_age + 1); x += kBBlock) s_gS[x] = 0.0;
+  if (ANY_LDS && a.do_gather)
+    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.gz_cur[x];
+  for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
+    a.gz_clr[x] = 0ull;
+  __syncthreads();
+  const int LB = S.LB, lane = tid & 63, gl = lane & (LB - 1), gq = lane / LB;
+  const Slots<SPL> sl = lane_slots<SPL>(S, gl);
+  const int t = a.t;
+  const int W = P.tau_E + P.tau_I;
+  const int64_t NB = (int64_t)G.N * S.B;
+  const __amdgpu_buffer_rsrc_t rg = rsrc(a.g_cur, NB * 4);
+
+  for (;;) {
+    const int tile = next_tile(a.work, gl, gq, LB);
+    if (tile >= G.n_btiles) break;
+    const TileInfo ti = G.btiles[tile];
+    int64_t e = ti.e0;
+    int64_t e_next = G.row_ptr[ti.r0 + 1];
+    for (int r = ti.r0; r < ti.r1; ++r) {
+      const int64_t e1 = e_next;
+      if (r + 1 < ti.r1) e_next = G.row_ptr[r + 2];
+      double acc[SPL];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) acc[s] = 0.0;
+      if (a.do_gather) {
+        for (; e < e1; e += kBUnroll) {
+          uint32_t c[kBUnroll];
+          float w[kBUnroll];
+#pragma unroll
+          for (int k = 0; k < kBUnroll; ++k) {
+            const int64_t pos = e + k < e1 ? e + k : e1 - 1;
+            c[k] = (uint32_t)G.col[pos];
+            w[k] = G.w[pos];
+          }
+          uint32_t v[kBUnroll][SPL];
+#pragma unroll
+          for (int k = 0; k < kBUnroll; ++k) {
+            const bool need = (e + k < e1) && any_bit<ANY_LDS>(s_any, a.gz_cur, c[k]);
+#pragma unroll
+            for (int s = 0; s < SPL; ++s)
+              v[k][s] = rload(rg, need ? (c[k] * (uint32_t)S.B + (uint32_t)sl.b[s]) * 4u : kOut);
+          }
+#pragma unroll
+          for (int k = 0; k < kBUnroll; ++k)
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) acc[s] += (double)w[k] * (double)__builtin_bit_cast(float, v[k][s]);
+        }
+      }
+      e = e1;
+      const int p = pop_of_agent(G, r);
+      const uint32_t loc = (uint32_t)(r - G.pop_off[p]);
+      const int age = G.age[r];
+      unsigned long long bz[SPL];
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        float gnew = 0.f;
+        if (sl.ok[s]) {
+          const int b = sl.b[s], set = sl.set[s];
+          const int64_t idx = (int64_t)r * S.B + b;
+          if (a.do_gather) a.ring[(int64_t)(t % W) * NB + idx] = (float)acc[s];
+          const double Sbar1 = (double)a.Sbar[idx];
+          const double m = (double)P.m[set];
+          if (t >= 1) {
+            const int d = t - 1;
+            double sE = 0.0, sI = 0.0;
+            for (int k = 1; k <= W; ++k) {
+              const double v = (double)a.ring[(int64_t)((d + k) % W) * NB + idx];
+              if (k <= P.tau_E) sE += v; else sI += v;
+            }
+            const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)b * P.K + d + W] : 0.0;
+            const uint32_t fl = a.fl_st[idx];
+            const double Aday = (double)a.A_st[idx];
+            const AdjOut ad = agent_adjoint(P, a.rng, sl.strm[s], d, set, p, loc, age, Aday, (double)(fl & 1u),
+                                            (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
+            a.Sbar[idx] = (float)ad.Sbar;
+            a.g_prev[idx] = (float)ad.g;
+            gnew = (float)ad.g;
+            if (ad.lam_bar != 0.0) atomicAdd(&s_gS[b * P.n_age + age], ad.lam_bar * Aday / (double)P.Z[p]);
+          } else {
+            double sI = 0.0;
+            for (int k = 0; k < P.tau_I; ++k) sI += (double)a.ring[(int64_t)(k % W) * NB + idx];
+            const double x0_bar = P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)b * P.K + P.tau_I - 1] : 0.0) - Sbar1;
+            const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, sl.strm[s]).x);
+            double y0, dy0;
+            relaxed_init((double)P.i0[set], u, P.tau, y0, dy0);
+            const double v = x0_bar * dy0;
+            if (v != 0.0) atomicAdd(&s_gi0[b], v);
+          }
+        }
+        bz[s] = __ballot(sl.ok[s] && gnew != 0.f);
+      }
+      if (gl == 0 && group_any<SPL>(bz, gq, LB)) atomicOr(&a.gz_next[r >> 6], 1ull << (r & 63));
+    }
+  }
+  __syncthreads();
+  const int slot = blockIdx.x & (kSlots - 1);
+  if (t >= 1) {
+    const int d = t - 1;
+    for (int x = tid; x < S.B * P.n_age; x += kBBlock) {
+      const double v = s_gS[x];
+      if (v != 0.0) {
+        const int set = (x / P.n_age) % S.n_sets, g = x % P.n_age;
+        atomicAdd(&a.gS[((int64_t)set * P.n_age + g) * kSlots + slot], v * (double)P.R[set * P.K + d]);
+      }
+    }
+    for (int b = tid; b < S.B; b += kBBlock) {
+      const int set = b % S.n_sets;
+      double acc = 0.0;
+      for (int g = 0; g < P.n_age; ++g) acc += s_gS[b * P.n_age + g] * (double)P.S[set * P.n_age + g];
+      if (acc != 0.0) atomicAdd(&a.gR[((int64_t)set * P.K + d) * kSlots + slot], acc);
+    }
+  } else {
+    for (int b = tid; b < S.B; b += kBBlock) {
+      const double v = s_gi0[b];
+      if (v != 0.0) atomicAdd(&a.gi0[(int64_t)(b % S.n_sets) * kSlots + slot], v);
+    }
+  }
+}
+
+template __global__ void k_binit<1>(BInitArgs);
+template __global__ void k_binit<2>(BInitArgs);
+template __global__ void k_binit<4>(BInitArgs);
+template __global__ void k_bmask<1>(BMaskArgs);
+template __global__ void k_bmask<2>(BMaskArgs);
+template __global__ void k_bmask<4>(BMaskArgs);
+template __global__ void k_bfwd<1, true>(BFwdArgs);
+template __global__ void k_bfwd<2, true>(BFwdArgs);
+template __global__ void k_bfwd<4, true>(BFwdArgs);
+template __global__ void k_bfwd<1, false>(BFwdArgs);
+template __global__ void k_bfwd<2, false>(BFwdArgs);
+template __global__ void k_bfwd<4, false>(BFwdArgs);
+template __global__ void k_bbwd<1, true>(BBwdArgs);
+template __global__ void k_bbwd<2, true>(BBwdArgs);
+template __global__ void k_bbwd<4, true>(BBwdArgs);
+template __global__ void k_bbwd<1, false>(BBwdArgs);
+template __global__ void k_bbwd<2, false>(BBwdArgs);
+template __global__ void k_bbwd<4, false>(BBwdArgs);
 
 }  // namespace gabm

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <string>
 
+#include "batched.h"
 #include "day_kernels.h"
 #include "sim_internal.h"
 #include "tile.h"
@@ -378,11 +379,22 @@ gabm_status gabm_er_daily(gabm_graph g, int32_t pop, const gabm_rng* rng, int32_
   return GABM_OK;
 }
 
-static gabm_status check_run(const gabm_run_desc* run) {
+static gabm_status check_run(const Graph& G, const gabm_params* p, const gabm_run_desc* run) {
   GABM_CHECK(run != nullptr, GABM_EINVAL, "run desc is NULL");
   GABM_CHECK(run->n_reps >= 1, GABM_EINVAL, "n_reps must be >= 1");
   GABM_CHECK(run->ckpt_every >= 0, GABM_EINVAL, "ckpt_every must be >= 0");
   GABM_CHECK(run->precision == GABM_F32 || run->precision == GABM_F64, GABM_EINVAL, "unknown precision");
+  const int64_t B = p->per_pop_params ? run->n_reps : (int64_t)p->n_sets * run->n_reps;
+  if (B > 1) {
+    GABM_CHECK(B <= kBMaxB, GABM_EUNSUPPORTED, "a batched run takes at most 256 simulations");
+    GABM_CHECK(!p->per_pop_params, GABM_EUNSUPPORTED,
+               "batched runs take one parameter set per simulation (per-population parameters need B = 1)");
+    GABM_CHECK(p->mode != GABM_SOFT, GABM_EUNSUPPORTED, "batched runs use hard states (PLAIN or HARD_ST)");
+    GABM_CHECK(run->precision == GABM_F32, GABM_EUNSUPPORTED, "batched runs store float state");
+    GABM_CHECK(G.er_off_h.empty() || G.er_off_h.back() == 0, GABM_EUNSUPPORTED,
+               "batched runs take static contact layers only (no daily random layer)");
+    GABM_CHECK((int64_t)G.N * B <= ((int64_t)1 << 29), GABM_EUNSUPPORTED, "a batched run needs N * B <= 2^29");
+  }
   return GABM_OK;
 }
 
@@ -391,7 +403,7 @@ gabm_status gabm_sim_workspace_size(gabm_graph g, const gabm_params* p, const ga
   DParams P;
   gabm_status rc = check_params(g->g, p, &P);
   if (rc != GABM_OK) return rc;
-  rc = check_run(run);
+  rc = check_run(g->g, p, run);
   if (rc != GABM_OK) return rc;
   return sim_workspace(g->g, p, run, bytes);
 }
@@ -402,10 +414,8 @@ gabm_status gabm_sim_create(gabm_graph g, const gabm_params* p, const gabm_run_d
   DParams P;
   gabm_status rc = check_params(g->g, p, &P);
   if (rc != GABM_OK) return rc;
-  rc = check_run(run);
+  rc = check_run(g->g, p, run);
   if (rc != GABM_OK) return rc;
-  const int64_t B = p->per_pop_params ? run->n_reps : (int64_t)p->n_sets * run->n_reps;
-  GABM_CHECK(B == 1, GABM_EUNSUPPORTED, "batched simulations (B > 1) are not available in this build");
   gabm_sim s = new (std::nothrow) gabm_sim_s();
   GABM_CHECK(s != nullptr, GABM_ENOMEM, "host allocation failed");
   rc = sim_create(g->g, p, run, s->s);

@@ -20,9 +20,10 @@ constexpr uint32_t kDayInit = 0xFFFFFFFFu;
 // persistent kernels: one 1024-thread block per compute unit holding a
 // one-bit-per-agent mask in LDS
 constexpr int kFastBlock = 1024;
-constexpr int kFastCap = 4096;     // contacts per tile
-constexpr int kFastRows = 1024;    // receivers per tile
 constexpr int kFastMaskWords = 16384;  // 64-bit words of LDS mask: up to 2^20 agents
+// receiver tiles of the batched kernels (one lane group per tile)
+constexpr int kBTileCap = 512;
+constexpr int kBTileRows = 64;
 // wave chunks of the edge-parallel neighbour sum: 64 lanes x 4 contacts
 constexpr int kChunk = 256;
 constexpr int kChunkShift = 8;
@@ -110,8 +111,8 @@ struct DGraph {
   const float* w;          // [E]
   const int32_t* tile_row; // [n_tiles+1]
   const TileInfo* tiles;   // [n_tiles]
-  const TileInfo* ftiles;  // [n_ftiles] tiles of the persistent kernels
-  int32_t n_ftiles;
+  const TileInfo* btiles;  // [n_btiles] tiles of the batched kernels
+  int32_t n_btiles;
   // edge-parallel form: sender | (rows starting at this contact) << 24, padded
   // with zero contacts to a multiple of kChunk; first row of each chunk
   const uint32_t* colp;    // [n_chunks * kChunk]

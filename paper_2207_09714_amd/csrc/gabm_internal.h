@@ -34,8 +34,8 @@ struct Graph {
   float* w = nullptr;
   int32_t* tile_row = nullptr;
   TileInfo* tiles = nullptr;
-  TileInfo* ftiles = nullptr;
-  int32_t n_ftiles = 0;
+  TileInfo* btiles = nullptr;
+  int32_t n_btiles = 0;
   uint32_t* colp = nullptr;
   float* wp = nullptr;
   uint32_t* chunk_row = nullptr;
@@ -47,7 +47,7 @@ struct Graph {
 
   DGraph view() const {
     DGraph g;
-    g.row_ptr = row_ptr; g.col = col; g.w = w; g.tile_row = tile_row; g.tiles = tiles; g.ftiles = ftiles; g.n_ftiles = n_ftiles; g.age = age;
+    g.row_ptr = row_ptr; g.col = col; g.w = w; g.tile_row = tile_row; g.tiles = tiles; g.btiles = btiles; g.n_btiles = n_btiles; g.age = age;
     g.colp = colp; g.wp = wp; g.chunk_row = chunk_row; g.n_chunks = n_chunks; g.pop_of = pop_of;
     g.pop_off = pop_off; g.er_off = er_off; g.N = N; g.n_pops = n_pops; g.n_tiles = n_tiles;
     g.er_total = er_off_h.empty() ? 0 : er_off_h.back();

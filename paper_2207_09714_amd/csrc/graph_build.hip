@@ -288,9 +288,9 @@ __global__ void k_weight_sum(const float* w, int64_t E, double* out) {
 }
 
 void Graph::release() {
-  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(tiles); hipFree(ftiles); hipFree(colp); hipFree(wp); hipFree(chunk_row); hipFree(age); hipFree(pop_of); hipFree(pop_off);
+  hipFree(row_ptr); hipFree(col); hipFree(w); hipFree(tile_row); hipFree(tiles); hipFree(btiles); hipFree(colp); hipFree(wp); hipFree(chunk_row); hipFree(age); hipFree(pop_of); hipFree(pop_off);
   hipFree(er_off);
-  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; tiles = nullptr; ftiles = nullptr; colp = nullptr; wp = nullptr; chunk_row = nullptr;
+  row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; tiles = nullptr; btiles = nullptr; colp = nullptr; wp = nullptr; chunk_row = nullptr;
   n_chunks = 0;
   age = nullptr; pop_of = nullptr;
   pop_off = nullptr; er_off = nullptr;
@@ -466,18 +466,18 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
   {
     std::vector<int32_t> ft;
     int32_t nl = 0, md = 0;
-    make_tiles(rp, ft, nl, md, kFastCap, kFastRows);
-    G.n_ftiles = (int32_t)ft.size() - 1;
-    std::vector<TileInfo> fi(G.n_ftiles);
-    for (int32_t k = 0; k < G.n_ftiles; ++k) {
+    make_tiles(rp, ft, nl, md, kBTileCap, kBTileRows);
+    G.n_btiles = (int32_t)ft.size() - 1;
+    std::vector<TileInfo> fi(G.n_btiles);
+    for (int32_t k = 0; k < G.n_btiles; ++k) {
       fi[k].r0 = ft[k];
       fi[k].r1 = ft[k + 1];
       fi[k].e0 = rp[ft[k]];
       fi[k].e1 = rp[ft[k + 1]];
       fi[k].pad0 = fi[k].pad1 = 0;
     }
-    GABM_HIP(dalloc(&G.ftiles, fi.size()));
-    GABM_HIP(hipMemcpyAsync(G.ftiles, fi.data(), sizeof(TileInfo) * fi.size(), hipMemcpyHostToDevice, st));
+    GABM_HIP(dalloc(&G.btiles, fi.size()));
+    GABM_HIP(hipMemcpyAsync(G.btiles, fi.data(), sizeof(TileInfo) * fi.size(), hipMemcpyHostToDevice, st));
     GABM_HIP(hipStreamSynchronize(st));
   }
   // edge-parallel form for the persistent kernels (senders below 2^24)

@@ -78,7 +78,7 @@ void Sim::release() {
   bwd_graphs.clear();
   void* ps[] = {rec[0], rec[1], maskI[0], maskI[1], maskI[2], maskE[0], maskE[1], maskE[2], A_er, Sv, x0, xi_ring,
                 inf[0], inf[1], A_st, fl_st, S_st, ck_rec, ck_soft, cnt, cnt0, drm, Dbar, Dbar_eff, ring, Sbar, g[0], g[1],
-                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece};
+                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece, anyI[0], anyI[1], anyI[2], wq};
   for (void* p : ps) hipFree(p);
 }
 
@@ -124,6 +124,21 @@ static Layout layout(const Graph& G, int B, int n_out, int n_sets, int K, int W,
   return L;
 }
 
+// buffers of the persistent path (B = 1) and of the batched path (B > 1)
+static size_t extra_bytes(const Sim& s) {
+  const Graph& G = *s.G;
+  size_t b = 3 * s.gz_bytes;
+  if (s.fast_fwd_ok || s.fast_bwd_ok) b += (size_t)G.N * 8 + (size_t)G.n_chunks * 16;
+  if (s.B > 1) b += 3 * (size_t)s.any_words * 8 + (size_t)(3 * s.K + 1) * 4;
+  return b;
+}
+
+static int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
 static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_run_desc* run) {
   s.G = const_cast<Graph*>(&G);
   s.n_sets = p->n_sets;
@@ -161,7 +176,14 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
   } else {
     s.bw = (s.B + 31) / 32;
     s.mask_words = ((int64_t)G.N * s.bw + 1) / 2 + 2;
+    s.LB = s.B > 32 ? 64 : next_pow2(s.B);
+    s.spl = s.B <= 64 ? 1 : (s.B <= 128 ? 2 : 4);
+    s.any_words = (int64_t)G.N / 64 + 2;
+    s.b_any_lds = s.any_words <= kBAnyLdsWords;
   }
+  s.gz_bytes = 0;
+  if (s.fast_bwd_ok) s.gz_bytes = (size_t)s.mask_words * 8;
+  if (s.B > 1 && s.mode != GABM_PLAIN) s.gz_bytes = (size_t)s.any_words * 8;
 }
 
 gabm_status sim_workspace(const Graph& G, const gabm_params* p, const gabm_run_desc* run, size_t* bytes) {
@@ -169,7 +191,39 @@ gabm_status sim_workspace(const Graph& G, const gabm_params* p, const gabm_run_d
   sim_shape(s, G, p, run);
   Layout L = layout(G, s.B, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz,
                     G.er_off_h.back() > 0, s.mask_words);
-  *bytes = L.total();
+  *bytes = L.total() + extra_bytes(s);
+  return GABM_OK;
+}
+
+// launch sizes of the batched kernels: enough resident blocks to fill every
+// compute unit (the day kernels take receiver tiles from a counter)
+template <class K>
+static int resident_grid(K kernel, size_t lds, int n_cu) {
+  int nb = 0;
+  if (lds > 65536) hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, kBBlock, lds) != hipSuccess || nb < 1) nb = 1;
+  return nb * std::max(1, n_cu);
+}
+
+template <int SPL>
+static void batched_grids(Sim& s) {
+  const size_t lf = bfwd_lds(s.B, s.any_words, s.b_any_lds);
+  const size_t lb = bbwd_lds(s.B, s.n_age, s.any_words, s.b_any_lds);
+  s.bgrid_i = resident_grid(k_binit<SPL>, 0, s.n_cu);
+  if (s.b_any_lds) {
+    s.bgrid_f = resident_grid(k_bfwd<SPL, true>, lf, s.n_cu);
+    s.bgrid_b = resident_grid(k_bbwd<SPL, true>, lb, s.n_cu);
+  } else {
+    s.bgrid_f = resident_grid(k_bfwd<SPL, false>, lf, s.n_cu);
+    s.bgrid_b = resident_grid(k_bbwd<SPL, false>, lb, s.n_cu);
+  }
+}
+
+static gabm_status batched_setup(Sim& s) {
+  if (s.spl == 1) batched_grids<1>(s);
+  else if (s.spl == 2) batched_grids<2>(s);
+  else batched_grids<4>(s);
+  GABM_HIP(hipGetLastError());
   return GABM_OK;
 }
 
@@ -224,11 +278,19 @@ gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc
   AL(s.gR, L.gR);
   AL(s.gS, L.gS);
   AL(s.gi0, L.gi0);
-  if (s.fast_bwd_ok)
-    for (int k = 0; k < 3; ++k) AL(s.gz[k], (size_t)s.mask_words * 8);
+  for (int k = 0; k < 3; ++k) AL(s.gz[k], s.gz_bytes);
   if (s.fast_fwd_ok || s.fast_bwd_ok) {
     AL(s.Abuf, (size_t)G.N * 8);
     AL(s.piece, (size_t)G.n_chunks * 2 * 8);
+  }
+  if (s.B > 1) {
+    for (int k = 0; k < 3; ++k) AL(s.anyI[k], (size_t)s.any_words * 8);
+    AL(s.wq, (size_t)(3 * s.K + 1) * 4);
+    gabm_status rc = batched_setup(s);
+    if (rc != GABM_OK) {
+      s.release();
+      return rc;
+    }
   }
 #undef AL
   return GABM_OK;
@@ -440,6 +502,114 @@ static void fin_bwd(Sim& s, const gabm_grads* out, hipStream_t st) {
   hipLaunchKernelGGL(k_fin_bwd, dim3(s.n_sets), dim3(kBlock), 0, st, f);
 }
 
+// batched path (B > 1) ----------------------------------------------------------
+
+static BSims bsims(const Sim& s, uint32_t stream) {
+  BSims S;
+  S.B = s.B;
+  S.n_sets = s.n_sets;
+  S.indep = s.indep;
+  S.stream0 = stream;
+  S.bw = s.bw;
+  S.LB = s.LB;
+  return S;
+}
+
+static void bt_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStream_t st) {
+  for (int k = 0; k < 3; ++k) fill0(s.anyI[k], (size_t)s.any_words * 8, st);
+  BInitArgs a;
+  a.G = s.G->view(); a.P = P; a.rng = rng; a.S = bsims(s, stream);
+  a.rec = s.rec[0];
+  a.mI = (uint32_t*)s.maskI[0];
+  a.mE = P.TE != 0.0 ? (uint32_t*)s.maskE[0] : nullptr;
+  a.any = s.anyI[0];
+  a.cnt0 = s.cnt0;
+  s.cur = 0;
+  if (s.spl == 1) hipLaunchKernelGGL(k_binit<1>, dim3(s.bgrid_i), dim3(kBBlock), 0, st, a);
+  else if (s.spl == 2) hipLaunchKernelGGL(k_binit<2>, dim3(s.bgrid_i), dim3(kBBlock), 0, st, a);
+  else hipLaunchKernelGGL(k_binit<4>, dim3(s.bgrid_i), dim3(kBBlock), 0, st, a);
+}
+
+template <int SPL>
+static void bt_launch_fwd(Sim& s, const BFwdArgs& a, hipStream_t st) {
+  const size_t lds = bfwd_lds(s.B, s.any_words, s.b_any_lds);
+  if (s.b_any_lds) hipLaunchKernelGGL((k_bfwd<SPL, true>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+  else hipLaunchKernelGGL((k_bfwd<SPL, false>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+}
+
+template <int SPL>
+static void bt_launch_bwd(Sim& s, const BBwdArgs& a, hipStream_t st) {
+  const size_t lds = bbwd_lds(s.B, s.n_age, s.any_words, s.b_any_lds);
+  if (s.b_any_lds) hipLaunchKernelGGL((k_bbwd<SPL, true>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+  else hipLaunchKernelGGL((k_bbwd<SPL, false>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+}
+
+// one forward day of all simulations; `replay` = recomputation inside the reverse pass
+static void bt_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t, int slot, bool count, bool replay,
+                       hipStream_t st) {
+  const bool withE = P.TE != 0.0;
+  BFwdArgs a;
+  a.G = s.G->view(); a.P = P; a.rng = rng; a.S = bsims(s, stream); a.t = t;
+  a.rec_in = s.rec[s.cur];
+  a.rec_out = s.rec[1 - s.cur];
+  a.mI = (const uint32_t*)s.maskI[t & 1];
+  a.mE = withE ? (const uint32_t*)s.maskE[t & 1] : nullptr;
+  a.mI_next = (uint32_t*)s.maskI[(t + 1) & 1];
+  a.mE_next = withE ? (uint32_t*)s.maskE[(t + 1) & 1] : nullptr;
+  a.any_cur = s.anyI[t % 3];
+  a.any_next = s.anyI[(t + 1) % 3];
+  a.any_clr = s.anyI[(t + 2) % 3];
+  a.any_words = s.any_words;
+  const bool store = slot >= 0 && s.mode != GABM_PLAIN;
+  a.A_st = store ? (float*)s.A_st + (int64_t)slot * s.NB : nullptr;
+  a.fl_st = store ? s.fl_st + (int64_t)slot * s.NB : nullptr;
+  a.cnt = count ? s.cnt : nullptr;
+  a.work = s.wq + (replay ? s.K + t : t);
+  KTime kt(s, st, GABM_KT_DAY_FWD);
+  if (s.spl == 1) bt_launch_fwd<1>(s, a, st);
+  else if (s.spl == 2) bt_launch_fwd<2>(s, a, st);
+  else bt_launch_fwd<4>(s, a, st);
+  s.cur = 1 - s.cur;
+}
+
+static void bt_restore(Sim& s, const DParams& P, int seg, int s0, hipStream_t st) {
+  copy_bytes(s.rec[s.cur], s.ck_rec + (int64_t)seg * s.NB, s.NB * 4, st);
+  for (int k = 0; k < 3; ++k) fill0(s.anyI[k], (size_t)s.any_words * 8, st);
+  BMaskArgs a;
+  a.G = s.G->view(); a.S = bsims(s, 0);
+  a.rec = s.rec[s.cur];
+  a.mI = (uint32_t*)s.maskI[s0 & 1];
+  a.mE = P.TE != 0.0 ? (uint32_t*)s.maskE[s0 & 1] : nullptr;
+  a.any = s.anyI[s0 % 3];
+  if (s.spl == 1) hipLaunchKernelGGL(k_bmask<1>, dim3(s.bgrid_i), dim3(kBBlock), 0, st, a);
+  else if (s.spl == 2) hipLaunchKernelGGL(k_bmask<2>, dim3(s.bgrid_i), dim3(kBBlock), 0, st, a);
+  else hipLaunchKernelGGL(k_bmask<4>, dim3(s.bgrid_i), dim3(kBBlock), 0, st, a);
+}
+
+// reverse step t of all simulations: gather of g^t (t < K), adjoint of day t-1
+static void bt_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t, int slot, hipStream_t st) {
+  BBwdArgs a;
+  a.G = s.G->view(); a.P = P; a.rng = rng; a.S = bsims(s, stream); a.t = t;
+  a.do_gather = t < s.K ? 1 : 0;
+  a.g_cur = (const float*)s.g[t & 1];
+  a.g_prev = (float*)s.g[(t + 1) & 1];
+  a.ring = (float*)s.ring;
+  a.Sbar = (float*)s.Sbar;
+  a.A_st = t >= 1 ? (const float*)s.A_st + (int64_t)slot * s.NB : nullptr;
+  a.fl_st = t >= 1 ? s.fl_st + (int64_t)slot * s.NB : nullptr;
+  a.Dbar = s.Dbar_eff;
+  a.gz_cur = s.gz[t % 3];
+  a.gz_next = s.gz[(t + 2) % 3];
+  a.gz_clr = s.gz[(t + 1) % 3];
+  a.any_words = s.any_words;
+  a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
+  a.work = s.wq + 2 * s.K + t;
+  KTime kt(s, st, GABM_KT_DAY_BWD);
+  if (s.spl == 1) bt_launch_bwd<1>(s, a, st);
+  else if (s.spl == 2) bt_launch_bwd<2>(s, a, st);
+  else bt_launch_bwd<4>(s, a, st);
+}
+
 static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st) {
   const int64_t n = (int64_t)sim_n_out(s) * s.K;
   hipLaunchKernelGGL(k_dbar_eff, dim3(blocks_capped(n)), dim3(kBlock), 0, st, sim_n_out(s), s.K, s.Dbar, lw, db,
@@ -447,7 +617,8 @@ static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st
   fill0(s.ring, (size_t)s.W * s.NB * s.rsz, st);
   fill0(s.Sbar, s.NB * s.rsz, st);
   fill0(s.infbar_er, s.infbar_er ? (size_t)s.NB * 8 : 0, st);
-  for (int k = 0; k < 3; ++k) fill0(s.gz[k], s.gz[k] ? (size_t)s.mask_words * 8 : 0, st);
+  for (int k = 0; k < 3; ++k) fill0(s.gz[k], s.gz_bytes, st);
+  if (s.wq) fill0(s.wq + s.K, (size_t)(2 * s.K + 1) * 4, st);  // counters of replayed days and reverse steps
   fill0(s.gR, (size_t)s.n_sets * s.K * kSlots * 8, st);
   fill0(s.gS, (size_t)s.n_sets * s.n_age * kSlots * 8, st);
   fill0(s.gi0, (size_t)s.n_sets * kSlots * 8, st);
@@ -467,29 +638,39 @@ static void run_forward(Sim& s, const DParams& P, Rng rng, uint32_t stream, cons
       if (s.n_seg > 1 && s.mode != GABM_PLAIN && t % s.ckpt == 0 && t < last_s0) b1_snapshot<RT>(s, t / s.ckpt, false, st);
       b1_day_fwd<RT>(s, P, rng, stream, t, t >= last_s0 ? t - last_s0 : -1, true, st);
     }
-    b1_fin_fwd<RT>(s, P, target, stride, out, st);
   } else {
-    batched_forward<RT>(s, P, rng, target, stride, out, st);
+    fill0(s.wq, (size_t)s.K * 4, st);
+    bt_init(s, P, rng, stream, st);
+    for (int t = 0; t < s.K; ++t) {
+      if (s.n_seg > 1 && s.mode != GABM_PLAIN && t % s.ckpt == 0 && t < last_s0) b1_snapshot<RT>(s, t / s.ckpt, false, st);
+      bt_day_fwd(s, P, rng, stream, t, t >= last_s0 ? t - last_s0 : -1, true, false, st);
+    }
   }
+  b1_fin_fwd<RT>(s, P, target, stride, out, st);
 }
 
 template <typename RT>
 static void run_backward(Sim& s, const DParams& P, Rng rng, uint32_t stream, const double* lw, const double* db,
                          const gabm_grads* out, hipStream_t st) {
   bwd_reset(s, lw, db, st);
-  if (s.B != 1) {
-    batched_backward<RT>(s, P, rng, out, st);
-    return;
-  }
+  const bool bt = s.B != 1;
   for (int seg = s.n_seg - 1; seg >= 0; --seg) {
     const int s0 = seg * s.ckpt, s1 = std::min(s.K, s0 + s.ckpt);
     if (seg != s.n_seg - 1) {
-      b1_restore<RT>(s, seg, s0, st);
-      for (int d = s0; d < s1; ++d) b1_day_fwd<RT>(s, P, rng, stream, d, d - s0, false, st);
+      if (bt) bt_restore(s, P, seg, s0, st);
+      else b1_restore<RT>(s, seg, s0, st);
+      for (int d = s0; d < s1; ++d) {
+        if (bt) bt_day_fwd(s, P, rng, stream, d, d - s0, false, true, st);
+        else b1_day_fwd<RT>(s, P, rng, stream, d, d - s0, false, st);
+      }
     }
-    for (int t = s1; t > s0; --t) b1_day_bwd<RT>(s, P, rng, stream, t, t - 1 - s0, st);
+    for (int t = s1; t > s0; --t) {
+      if (bt) bt_day_bwd(s, P, rng, stream, t, t - 1 - s0, st);
+      else b1_day_bwd<RT>(s, P, rng, stream, t, t - 1 - s0, st);
+    }
   }
-  b1_day_bwd<RT>(s, P, rng, stream, 0, 0, st);
+  if (bt) bt_day_bwd(s, P, rng, stream, 0, 0, st);
+  else b1_day_bwd<RT>(s, P, rng, stream, 0, 0, st);
   fin_bwd(s, out, st);
 }
 
@@ -539,14 +720,17 @@ gabm_status sim_forward(Sim& s, const DParams& P, const gabm_rng* r, const doubl
                         const gabm_fwd_out* out, hipStream_t st) {
   const Rng rng = make_rng(r);
   const uint32_t stream = r->replicate;
+  s.indep = r->independent_sets ? 1 : 0;
   gabm_status rc;
   if (s.precision == GABM_F64)
     rc = execute(s, true, P.R, P.S, target, out ? out->counts : nullptr, out ? out->loss : nullptr,
-                 (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56)), st,
+                 (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56) ^
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
                  [&](hipStream_t cs) { run_forward<double>(s, P, rng, stream, target, stride, out, cs); });
   else
     rc = execute(s, true, P.R, P.S, target, out ? out->counts : nullptr, out ? out->loss : nullptr,
-                 (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56)), st,
+                 (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56) ^
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
                  [&](hipStream_t cs) { run_forward<float>(s, P, rng, stream, target, stride, out, cs); });
   if (rc == GABM_OK) {
     s.fwd_done = true;
@@ -562,14 +746,17 @@ gabm_status sim_backward(Sim& s, const DParams& P, const gabm_rng* r, const doub
   GABM_CHECK(s.mode != GABM_PLAIN, GABM_ESTATE, "gabm_sim_backward on a PLAIN (forward-only) simulation");
   const Rng rng = make_rng(r);
   const uint32_t stream = r->replicate;
+  s.indep = r->independent_sets ? 1 : 0;
   // a backward replays segments and so consumes the forward state
   s.fwd_done = false;
   if (s.precision == GABM_F64)
     return execute(s, false, P.R, lw, db, out->dR, out->di0,
-                   (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40)), st,
+                   (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
                    [&](hipStream_t cs) { run_backward<double>(s, P, rng, stream, lw, db, out, cs); });
   return execute(s, false, P.R, lw, db, out->dR, out->di0,
-                 (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40)), st,
+                 (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
                  [&](hipStream_t cs) { run_backward<float>(s, P, rng, stream, lw, db, out, cs); });
 }
 
@@ -580,19 +767,21 @@ static gabm_status day_fwd_t(Sim& s, const DParams& P, const gabm_rng* r, int da
                              const gabm_fwd_out* out, hipStream_t st) {
   const Rng rng = make_rng(r);
   const uint32_t stream = r->replicate;
+  s.indep = r->independent_sets ? 1 : 0;
   if (day == 0) {
     fill0(s.cnt, (size_t)sim_n_out(s) * s.K * kSlots * kCnt * 8, st);
     fill0(s.cnt0, (size_t)sim_n_out(s) * kSlots * kCnt * 8, st);
-    if (s.B == 1) b1_init<RT>(s, P, rng, stream, st);
-    else batched_init<RT>(s, P, rng, st);
+    if (s.B == 1) {
+      b1_init<RT>(s, P, rng, stream, st);
+    } else {
+      fill0(s.wq, (size_t)s.K * 4, st);
+      bt_init(s, P, rng, stream, st);
+    }
   }
   const int slot = s.ckpt == s.K ? day : -1;
   if (s.B == 1) b1_day_fwd<RT>(s, P, rng, stream, day, slot, true, st);
-  else batched_day_fwd<RT>(s, P, rng, day, slot, true, st);
-  if (day == s.K - 1) {
-    if (s.B == 1) b1_fin_fwd<RT>(s, P, target, stride, out, st);
-    else batched_fin_fwd(s, P, target, stride, out, st);
-  }
+  else bt_day_fwd(s, P, rng, stream, day, slot, true, false, st);
+  if (day == s.K - 1) b1_fin_fwd<RT>(s, P, target, stride, out, st);
   GABM_HIP(hipGetLastError());
   return GABM_OK;
 }
@@ -618,9 +807,10 @@ static gabm_status day_bwd_t(Sim& s, const DParams& P, const gabm_rng* r, int da
                              hipStream_t st) {
   const Rng rng = make_rng(r);
   const uint32_t stream = r->replicate;
+  s.indep = r->independent_sets ? 1 : 0;
   if (day == s.K) bwd_reset(s, nullptr, nullptr, st);
   if (s.B == 1) b1_day_bwd<RT>(s, P, rng, stream, day, day >= 1 ? day - 1 : 0, st);
-  else batched_day_bwd<RT>(s, P, rng, day, day >= 1 ? day - 1 : 0, st);
+  else bt_day_bwd(s, P, rng, stream, day, day >= 1 ? day - 1 : 0, st);
   if (day == 0) fin_bwd(s, out, st);
   GABM_HIP(hipGetLastError());
   return GABM_OK;

@@ -68,8 +68,18 @@ struct Sim {
   int schedule = 0;  // 0 auto, 1 tile kernels only
   bool fast_fwd_ok = false, fast_bwd_ok = false;
   unsigned long long* gz[3] = {nullptr, nullptr, nullptr};
+  size_t gz_bytes = 0;
   double* Abuf = nullptr;  // [N] neighbour sums handed from the gather to the agent pass
   double* piece = nullptr; // [2 * n_chunks] sums of rows crossing chunk boundaries
+
+  // batched runs (B > 1): lane mapping, 'any simulation' masks of the forward
+  // days (the reverse pass uses gz), per-launch tile counters, launch sizes
+  int32_t LB = 64, spl = 1, indep = 0;
+  int64_t any_words = 0;
+  bool b_any_lds = true;
+  unsigned long long* anyI[3] = {nullptr, nullptr, nullptr};
+  unsigned int* wq = nullptr;  // [3K+1]: forward days, replayed days, reverse steps
+  int bgrid_i = 0, bgrid_f = 0, bgrid_b = 0;
 
   int next_day = 0;     // forward progress for gabm_day_fwd
   int next_bwd = -1;    // reverse progress for gabm_day_bwd

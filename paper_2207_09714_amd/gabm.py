@@ -262,8 +262,8 @@ class Simulator:
         t = t.to(_dev())
         return t, (0 if t.dim() == 1 else K)
 
-    def forward(self, params: ParamBlock, seed=0, replicate=0, target=None, stream=None):
-        rng = make_rng(seed, replicate)
+    def forward(self, params: ParamBlock, seed=0, replicate=0, target=None, stream=None, independent_sets=False):
+        rng = make_rng(seed, replicate, independent_sets)
         tgt, stride = self._target(target, self.K)
         self._keep = (params, tgt)
         out = self._out()
@@ -271,8 +271,9 @@ class Simulator:
                                      C.byref(out), C.c_void_p(_stream(stream))))
         return dict(counts=self.counts, drm=self.drm, deaths=self.deaths, loss=self.loss)
 
-    def backward(self, params: ParamBlock, seed=0, replicate=0, loss_weight=None, deaths_bar=None, stream=None):
-        rng = make_rng(seed, replicate)
+    def backward(self, params: ParamBlock, seed=0, replicate=0, loss_weight=None, deaths_bar=None, stream=None,
+                 independent_sets=False):
+        rng = make_rng(seed, replicate, independent_sets)
         lw = None if loss_weight is None else loss_weight.to(torch.float64).contiguous()
         db = None if deaths_bar is None else deaths_bar.to(torch.float64).contiguous()
         self._keep_b = (params, lw, db)
@@ -281,16 +282,16 @@ class Simulator:
                                       C.byref(g), C.c_void_p(_stream(stream))))
         return dict(dR=self.dR, dS=self.dS, dm=self.dm, di0=self.di0)
 
-    def day_fwd(self, params: ParamBlock, day, seed=0, replicate=0, target=None, stream=None):
-        rng = make_rng(seed, replicate)
+    def day_fwd(self, params: ParamBlock, day, seed=0, replicate=0, target=None, stream=None, independent_sets=False):
+        rng = make_rng(seed, replicate, independent_sets)
         tgt, stride = self._target(target, self.K)
         self._keep = (params, tgt)
         out = self._out()
         check(lib().gabm_day_fwd(self.handle, C.byref(params.c), C.byref(rng), int(day), _ptr(tgt), stride,
                                  C.byref(out), C.c_void_p(_stream(stream))))
 
-    def day_bwd(self, params: ParamBlock, day, seed=0, replicate=0, stream=None):
-        rng = make_rng(seed, replicate)
+    def day_bwd(self, params: ParamBlock, day, seed=0, replicate=0, stream=None, independent_sets=False):
+        rng = make_rng(seed, replicate, independent_sets)
         g = self._grads()
         check(lib().gabm_day_bwd(self.handle, C.byref(params.c), C.byref(rng), int(day), C.byref(g),
                                  C.c_void_p(_stream(stream))))
