@@ -201,6 +201,53 @@ def cpu_baseline(wl, days: int):
             "host_nproc": os.cpu_count()}
 
 
+def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
+    """The batched workload: 64 parameter sets x 2 replicates on one shared
+    250,000-agent graph, 45 days, differentiable forward+backward and the plain
+    forward of the same batch.  The loss target is all-zero daily deaths (the
+    target only sets the values of the adjoints, not the work)."""
+    from synth import make_workload
+
+    wl = make_workload("c4a")
+    g = gabm.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, n_age=8,
+                   pop_offsets=wl.pop.pop_offsets)
+    info = g.info()
+    E, K, B = info["n_edges"], wl.K, wl.n_sets * wl.n_reps
+    tgt = torch.zeros(K, dtype=torch.float64, device="cuda")
+    out = {"workload": f"c4a: {wl.n_agents} agents, {E} directed contacts per day, {K} days, "
+                       f"{wl.n_sets} parameter sets x {wl.n_reps} replicates = {B} simulations on one graph",
+           "n_agents": wl.n_agents, "edges_per_day": E, "days": K, "sims": B}
+    for name, mode in (("diff", gabm.HARD_ST), ("plain", gabm.PLAIN)):
+        sim = gabm.Simulator(g, n_sets=wl.n_sets, n_reps=wl.n_reps, K=K, Z=wl.Z, mode=mode,
+                             ckpt_every=wl.ckpt_every, use_hip_graph=not eager, time_kernels=eager, tau_g=wl.tau_g)
+        pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+
+        def step():
+            sim.forward(pb, seed=wl.seed, target=tgt)
+            if mode != gabm.PLAIN:
+                sim.backward(pb, seed=wl.seed)
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        if eager:
+            sim.kernel_times(reset=True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        leg = {"ms_per_run": dt * 1e3, "value": E * K * B / dt, "unit": "edge-days/s", "sim_days_per_s": K * B / dt}
+        if eager:
+            kt = sim.kernel_times(reset=True)
+            leg["kernels"] = {k: {"launches_per_run": v["launches"] / steps, "avg_ms": v["ms"] / v["launches"]}
+                              for k, v in kt.items() if v["launches"]}
+        if mode != gabm.PLAIN:
+            leg["workspace_bytes"] = sim.workspace_size()
+        out[name] = leg
+        del sim
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -211,7 +258,8 @@ def main():
                     help="eager launches with HIP-event kernel timing, or the day loop captured in hipGraphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-days", type=int, default=30)
-    ap.add_argument("--only", choices=["diff", "plain", "copy"], default=None,
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched (c4a) legs")
+    ap.add_argument("--only", choices=["diff", "plain", "copy", "batched"], default=None,
                     help="run a single leg (for profiler runs)")
     ap.add_argument("--traffic-from", default=None, metavar="DIR",
                     help="no run: turn the rocprofv3 --pmc runs under DIR (fetch/ write/ copy_fetch/ copy_write/) "
@@ -253,6 +301,11 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n}))
+        return
+
+    eager = args.launch == "eager"
+    if args.only == "batched":
+        print(json.dumps({"batched": batched_legs(gabm, torch, args.steps, args.warmup, eager)}), flush=True)
         return
 
     t_gen = time.perf_counter()
@@ -302,6 +355,9 @@ def main():
         res["plain_s"] = timed(simp, pbp, False)
         res["kt_plain"] = simp.kernel_times(reset=True) if eager else None
         del simp
+
+    if args.only is None and not args.no_batched:
+        res["batched"] = batched_legs(gabm, torch, max(1, args.steps // 2), max(1, args.warmup), eager)
 
     if args.only is not None:
         print(json.dumps({k: v for k, v in res.items()}), flush=True)
@@ -366,6 +422,8 @@ def main():
                            "alg_bytes_per_launch": d["alg_bytes_per_launch"], "avg_launch_ms": d["avg_ms"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_days)
+    if "batched" in res:
+        out["batched"] = res["batched"]
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
                             "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
     print(json.dumps(out), flush=True)

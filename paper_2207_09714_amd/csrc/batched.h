@@ -2,7 +2,10 @@
 // (several parameter sets and replicates of Section 3.2's calibration, one
 // launch per day for all of them).
 //
-// State is batch-minor: value of simulation b of agent i at i * B + b.  A
+// State is batch-minor: value of simulation b of agent i at i * B + b (the
+// wide kernels for B > 32 keep their per-simulation float vectors -- stored
+// day, window ring, S adjoint, rate adjoint -- lane-interleaved instead, see
+// batched.hip).  A
 // receiver row is processed by a group of LB lanes (LB = 64 for B > 32, else
 // the next power of two >= B); lane l of the group carries simulations
 // l, l + 64, ... (SPL = ceil(B / 64) of them), so the contact stream of a
@@ -105,7 +108,11 @@ __global__ void k_bmask(BMaskArgs a);
 template <int SPL, bool ANY_LDS>
 __global__ void k_bfwd(BFwdArgs a);
 template <int SPL, bool ANY_LDS>
+__global__ void k_bfwd64(BFwdArgs a);
+template <int SPL, bool ANY_LDS>
 __global__ void k_bbwd(BBwdArgs a);
+template <int SPL, bool ANY_LDS>
+__global__ void k_bbwd64(BBwdArgs a);
 
 // dynamic LDS bytes of the day kernels
 inline size_t bfwd_lds(int B, int64_t any_words, bool any_lds) {

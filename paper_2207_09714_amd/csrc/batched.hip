@@ -64,6 +64,67 @@ __device__ __forceinline__ Slots<SPL> lane_slots(const BSims& S, int gl) {
   return o;
 }
 
+// Lane-interleaved layout of the per-simulation vectors of the wide kernels
+// (B > 32): entry of simulation lane + 64 s of agent r at (r * 64 + lane) * SPL + s,
+// so a lane moves all its simulations with one vector access.
+template <int SPL>
+__device__ __forceinline__ int64_t il_index(int64_t r, int lane, int s) {
+  return (r * 64 + lane) * SPL + s;
+}
+template <int SPL>
+__device__ __forceinline__ void il_load(const float* p, float (&o)[SPL]) {
+  if constexpr (SPL == 1) {
+    o[0] = *p;
+  } else if constexpr (SPL == 2) {
+    const float2 v = *(const float2*)p;
+    o[0] = v.x; o[1] = v.y;
+  } else {
+    const float4 v = *(const float4*)p;
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  }
+}
+template <int SPL>
+__device__ __forceinline__ void il_store(float* p, const float (&v)[SPL]) {
+  if constexpr (SPL == 1) {
+    *p = v[0];
+  } else if constexpr (SPL == 2) {
+    *(float2*)p = make_float2(v[0], v[1]);
+  } else {
+    *(float4*)p = make_float4(v[0], v[1], v[2], v[3]);
+  }
+}
+template <int SPL>
+__device__ __forceinline__ void il_load_bytes(const uint8_t* p, uint32_t (&o)[SPL]) {
+  if constexpr (SPL == 1) {
+    o[0] = *p;
+  } else if constexpr (SPL == 2) {
+    const uint32_t v = *(const uint16_t*)p;
+    o[0] = v & 0xFFu; o[1] = v >> 8;
+  } else {
+    const uint32_t v = *(const uint32_t*)p;
+    o[0] = v & 0xFFu; o[1] = (v >> 8) & 0xFFu; o[2] = (v >> 16) & 0xFFu; o[3] = v >> 24;
+  }
+}
+// SPL floats of a lane from a raw buffer (zeros for an offset out of range).
+// The wide loads are read back through bit casts to plain words: indexing
+// their vector result directly made the compiler narrow the load to its first
+// word.
+struct Words2 { uint32_t x[2]; };
+struct Words4 { uint32_t x[4]; };
+template <int SPL>
+__device__ __forceinline__ void il_rload(__amdgpu_buffer_rsrc_t r, uint32_t off, float (&o)[SPL]) {
+  if constexpr (SPL == 1) {
+    o[0] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+  } else if constexpr (SPL == 2) {
+    const Words2 v = __builtin_bit_cast(Words2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    o[0] = __builtin_bit_cast(float, v.x[0]); o[1] = __builtin_bit_cast(float, v.x[1]);
+  } else {
+    const Words4 v = __builtin_bit_cast(Words4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[j] = __builtin_bit_cast(float, v.x[j]);
+  }
+}
+
 // this group's bits of a wave ballot (bit k = lane k of the group)
 __device__ __forceinline__ unsigned long long group_bits(unsigned long long bal, int gq, int LB) {
   return LB == 64 ? bal : (bal >> (gq * LB)) & ((1ull << LB) - 1ull);
@@ -105,6 +166,62 @@ __device__ __forceinline__ int next_tile(unsigned int* work, int gl, int gq, int
   int tile = 0;
   if (gl == 0) tile = (int)atomicAdd(work, 1u);
   return __shfl(tile, gq * LB);
+}
+
+// The forward day of receiver r in every simulation of the calling lane
+// group, from its neighbour sums: draw, progress, stored values, the day-t+1
+// mask words and 'any' bit, per-lane counts.
+template <int SPL, bool IL>
+__device__ __forceinline__ void fwd_agent(const BFwdArgs& a, const Slots<SPL>& sl, int gl, int gq, int r,
+                                          const double (&aI)[SPL], const double (&aE)[SPL], bool withE,
+                                          unsigned int (&cnt)[SPL][6]) {
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const BSims& S = a.S;
+  const int p = pop_of_agent(G, r);
+  const uint32_t loc = (uint32_t)(r - G.pop_off[p]);
+  const int age = G.age[r];
+  unsigned long long bI[SPL], bE[SPL];
+#pragma unroll
+  for (int s = 0; s < SPL; ++s) {
+    uint32_t newst = ST_S;
+    if (sl.ok[s]) {
+      const int64_t idx = (int64_t)r * S.B + sl.b[s];
+      const double A = P.TI * aI[s] + (withE ? P.TE * aE[s] : 0.0);
+      const HardDay hd = hard_agent_day(P, a.rng, sl.strm[s], a.t, sl.set[s], p, loc, age, A, a.rec_in[idx], nullptr);
+      a.rec_out[idx] = hd.rec;
+      const int64_t sidx = IL ? il_index<SPL>(r, gl, s) : idx;
+      if (a.A_st) a.A_st[sidx] = (float)A;
+      if (a.fl_st) a.fl_st[sidx] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
+      newst = hd.newst;
+      cnt[s][newst] += 1u;
+      if (hd.removed) cnt[s][5] += 1u;
+    }
+    bI[s] = __ballot(sl.ok[s] && newst == ST_I);
+    bE[s] = __ballot(sl.ok[s] && newst == ST_E);
+  }
+  put_bits<SPL>(a.mI_next, r, S, gl, gq, bI);
+  if (withE) put_bits<SPL>(a.mE_next, r, S, gl, gq, bE);
+  const bool act = group_any<SPL>(bI, gq, S.LB) || (withE && group_any<SPL>(bE, gq, S.LB));
+  if (gl == 0 && act) atomicOr(&a.any_next[r >> 6], 1ull << (r & 63));
+}
+
+// per-lane counts of a block into the day's FP64 aggregates
+template <int SPL>
+__device__ __forceinline__ void fwd_counts(const BFwdArgs& a, const Slots<SPL>& sl, unsigned int* s_cnt,
+                                           const unsigned int (&cnt)[SPL][6]) {
+#pragma unroll
+  for (int s = 0; s < SPL; ++s)
+    if (sl.ok[s])
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (cnt[s][c]) atomicAdd(&s_cnt[sl.b[s] * 6 + c], cnt[s][c]);
+  __syncthreads();
+  const int slot = blockIdx.x & (kSlots - 1);
+  for (int x = threadIdx.x; x < a.S.B * 6; x += kBBlock) {
+    const unsigned int v = s_cnt[x];
+    if (v) atomicAdd(&a.cnt[(((int64_t)(x / 6) * a.P.K + a.t) * kSlots + slot) * kCnt + x % 6], (double)v);
+  }
 }
 
 }  // namespace
@@ -256,48 +373,112 @@ __global__ void __launch_bounds__(kBBlock) k_bfwd(BFwdArgs a) {
           }
       }
       e = e1;
-      // the day of agent r in every simulation of this group
-      const int p = pop_of_agent(G, r);
-      const uint32_t loc = (uint32_t)(r - G.pop_off[p]);
-      const int age = G.age[r];
-      unsigned long long bI[SPL], bE[SPL];
-#pragma unroll
-      for (int s = 0; s < SPL; ++s) {
-        uint32_t newst = ST_S;
-        if (sl.ok[s]) {
-          const int64_t idx = (int64_t)r * S.B + sl.b[s];
-          const double A = P.TI * aI[s] + (withE ? P.TE * aE[s] : 0.0);
-          const HardDay hd =
-              hard_agent_day(P, a.rng, sl.strm[s], a.t, sl.set[s], p, loc, age, A, a.rec_in[idx], nullptr);
-          a.rec_out[idx] = hd.rec;
-          if (a.A_st) a.A_st[idx] = (float)A;
-          if (a.fl_st) a.fl_st[idx] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
-          newst = hd.newst;
-          cnt[s][newst] += 1u;
-          if (hd.removed) cnt[s][5] += 1u;
-        }
-        bI[s] = __ballot(sl.ok[s] && newst == ST_I);
-        bE[s] = __ballot(sl.ok[s] && newst == ST_E);
-      }
-      put_bits<SPL>(a.mI_next, r, S, gl, gq, bI);
-      if (withE) put_bits<SPL>(a.mE_next, r, S, gl, gq, bE);
-      const bool act = group_any<SPL>(bI, gq, LB) || (withE && group_any<SPL>(bE, gq, LB));
-      if (gl == 0 && act) atomicOr(&a.any_next[r >> 6], 1ull << (r & 63));
+      fwd_agent<SPL, false>(a, sl, gl, gq, r, aI, aE, withE, cnt);
     }
   }
-  if (a.cnt == nullptr) return;
+  if (a.cnt != nullptr) fwd_counts<SPL>(a, sl, s_cnt, cnt);
+}
+
+// ----------------------------------------------------------------- forward day, B > 32 (one wave per tile)
+// Lanes are simulations (b = lane + 64 s).  A tile's contacts are read 64 at
+// a time, one per lane: the packed sender with its row-start count, the
+// weight, and every mask word of the sender (zero, without a memory request,
+// when the sender is infectious in no simulation).  A window therefore costs
+// a few vector memory instructions instead of several per contact; the wave
+// then walks the window's active contacts and row starts (two ballots) and
+// reads each contact's values from the lane that loaded them.
+template <int SPL, bool ANY_LDS>
+__global__ void __launch_bounds__(kBBlock, 4) k_bfwd64(BFwdArgs a) {
+  extern __shared__ unsigned long long lds[];
+  unsigned long long* s_any = lds;
+  unsigned int* s_cnt = (unsigned int*)(lds + (ANY_LDS ? a.any_words : 0));
+  const int tid = threadIdx.x;
+  const DGraph& G = a.G;
+  const BSims& S = a.S;
+  for (int x = tid; x < S.B * 6; x += kBBlock) s_cnt[x] = 0u;
+  if (ANY_LDS)
+    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.any_cur[x];
+  for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
+    a.any_clr[x] = 0ull;
+  __syncthreads();
+  constexpr int MW = 2 * SPL;  // mask words a lane may need (bw <= MW)
+  const int lane = tid & 63;
+  const bool upper = lane >= 32;
+  const Slots<SPL> sl = lane_slots<SPL>(S, lane);
+  const bool withE = a.mE != nullptr;
+  const int64_t mbytes = (int64_t)G.N * S.bw * 4;
+  const __amdgpu_buffer_rsrc_t rI = rsrc(a.mI, mbytes);
+  const __amdgpu_buffer_rsrc_t rE = rsrc(a.mE, mbytes);
+  unsigned int cnt[SPL][6];
 #pragma unroll
   for (int s = 0; s < SPL; ++s)
-    if (sl.ok[s])
 #pragma unroll
-      for (int c = 0; c < 6; ++c)
-        if (cnt[s][c]) atomicAdd(&s_cnt[sl.b[s] * 6 + c], cnt[s][c]);
-  __syncthreads();
-  const int slot = blockIdx.x & (kSlots - 1);
-  for (int x = tid; x < S.B * 6; x += kBBlock) {
-    const unsigned int v = s_cnt[x];
-    if (v) atomicAdd(&a.cnt[(((int64_t)(x / 6) * P.K + a.t) * kSlots + slot) * kCnt + x % 6], (double)v);
+    for (int c = 0; c < 6; ++c) cnt[s][c] = 0u;
+  double aI[SPL], aE[SPL];
+
+  for (;;) {
+    const int tile = next_tile(a.work, lane, 0, 64);
+    if (tile >= G.n_btiles) break;
+    const TileInfo ti = G.btiles[tile];
+    int open = ti.r0 - 1;  // receiver of the running sums (none yet)
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) aI[s] = aE[s] = 0.0;
+    // windows of 64 contacts, then one closing window without contacts whose
+    // single row-start event closes the open receiver and the empty ones after it
+    for (int64_t wb = ti.e0;; wb += 64) {
+      const bool fin = wb >= ti.e1;
+      const int nwin = fin ? 0 : (int)(ti.e1 - wb < 64 ? ti.e1 - wb : 64);
+      const bool okc = lane < nwin;
+      const int64_t pos = okc ? wb + lane : (fin ? ti.e0 : wb);
+      const uint32_t pk = okc ? G.colp[pos] : 0u;
+      const float wl = okc ? G.wp[pos] : 0.f;
+      const uint32_t c = pk & 0xFFFFFFu;
+      int adv = (int)(pk >> 24);
+      if (lane == 0) {
+        if (fin) adv = ti.r1 - open;
+        else if (wb == ti.e0) adv -= ti.pad0;  // rows of earlier tiles starting here
+      }
+      const bool need = okc && any_bit<ANY_LDS>(s_any, a.any_cur, c);
+      uint32_t mi[MW], me[MW];
+#pragma unroll
+      for (int q = 0; q < MW; ++q) {
+        const uint32_t off = (need && q < S.bw) ? (c * (uint32_t)S.bw + (uint32_t)q) * 4u : kOut;
+        mi[q] = rload(rI, off);
+        me[q] = withE ? rload(rE, off) : 0u;
+      }
+      const unsigned long long rs = __ballot(adv > 0);
+      const unsigned long long nd = __ballot(need);
+      unsigned long long todo = rs | nd;
+      while (todo) {
+        const int k = __builtin_ctzll(todo);
+        todo &= todo - 1ull;
+        if ((rs >> k) & 1ull) {
+          for (int na = __builtin_amdgcn_readlane(adv, k); na > 0; --na) {
+            if (open >= ti.r0) fwd_agent<SPL, true>(a, sl, lane, 0, open, aI, aE, withE, cnt);
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) aI[s] = aE[s] = 0.0;
+            ++open;
+          }
+        }
+        if ((nd >> k) & 1ull) {
+          const double wk = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wl), k));
+#pragma unroll
+          for (int s = 0; s < SPL; ++s) {
+            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)mi[2 * s], k);
+            const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)mi[2 * s + 1], k);
+            if ((((upper ? w1 : w0)) >> sl.bsh[s]) & 1u) aI[s] += wk;
+            if (withE) {
+              const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)me[2 * s], k);
+              const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)me[2 * s + 1], k);
+              if ((((upper ? e1 : e0)) >> sl.bsh[s]) & 1u) aE[s] += wk;
+            }
+          }
+        }
+      }
+      if (fin) break;
+    }
   }
+  if (a.cnt != nullptr) fwd_counts<SPL>(a, sl, s_cnt, cnt);
 }
 
 // ----------------------------------------------------------------- reverse step
@@ -431,6 +612,207 @@ __global__ void __launch_bounds__(kBBlock) k_bbwd(BBwdArgs a) {
   }
 }
 
+// ----------------------------------------------------------------- reverse step, B > 32 (one wave per tile)
+// Lanes are simulations; the per-simulation vectors use the lane-interleaved
+// layout, so the rate adjoints of one contact's sender are a single
+// SPL-float load per lane.  Contacts are read 64 at a time, one per lane
+// (packed sender with row starts, weight); the wave walks the window's row
+// segments, gathering up to kBGather active senders of a segment at once.
+constexpr int kBGather = 16;
+
+template <int SPL>
+__device__ __forceinline__ void bwd_agent64(const BBwdArgs& a, const Slots<SPL>& sl, int lane, int r,
+                                            const double (&acc)[SPL], int64_t NV, double* s_gS, double* s_gi0) {
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const int t = a.t;
+  const int W = P.tau_E + P.tau_I;
+  const int p = pop_of_agent(G, r);
+  const uint32_t loc = (uint32_t)(r - G.pop_off[p]);
+  const int age = G.age[r];
+  const int64_t il = il_index<SPL>(r, lane, 0);
+  if (a.do_gather) {
+    float v[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) v[s] = (float)acc[s];
+    il_store<SPL>(a.ring + (int64_t)(t % W) * NV + il, v);
+  }
+  float sb[SPL];
+  il_load<SPL>(a.Sbar + il, sb);
+  bool gnz = false;
+  if (t >= 1) {
+    const int d = t - 1;
+    double sE[SPL], sI[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) sE[s] = sI[s] = 0.0;
+    for (int k = 1; k <= W; ++k) {
+      float v[SPL];
+      il_load<SPL>(a.ring + (int64_t)((d + k) % W) * NV + il, v);
+#pragma unroll
+      for (int s = 0; s < SPL; ++s) {
+        if (k <= P.tau_E) sE[s] += (double)v[s]; else sI[s] += (double)v[s];
+      }
+    }
+    float Ad[SPL];
+    uint32_t fl[SPL];
+    il_load<SPL>(a.A_st + il, Ad);
+    il_load_bytes<SPL>(a.fl_st + il, fl);
+    float sb_new[SPL], g_new[SPL];
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      sb_new[s] = sb[s];
+      g_new[s] = 0.f;
+      if (sl.ok[s]) {
+        const int b = sl.b[s], set = sl.set[s];
+        const double drm_bar = (d + W < P.K) ? (double)P.m[set] * a.Dbar[(int64_t)b * P.K + d + W] : 0.0;
+        const double Aday = (double)Ad[s];
+        const AdjOut ad = agent_adjoint(P, a.rng, sl.strm[s], d, set, p, loc, age, Aday, (double)(fl[s] & 1u),
+                                        (double)((fl[s] >> 1) & 1u), false, sE[s], sI[s], (double)sb[s], drm_bar);
+        sb_new[s] = (float)ad.Sbar;
+        g_new[s] = (float)ad.g;
+        if (g_new[s] != 0.f) gnz = true;
+        if (ad.lam_bar != 0.0) atomicAdd(&s_gS[b * P.n_age + age], ad.lam_bar * Aday / (double)P.Z[p]);
+      }
+    }
+    il_store<SPL>(a.Sbar + il, sb_new);
+    il_store<SPL>(a.g_prev + il, g_new);
+  } else {
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) {
+      if (!sl.ok[s]) continue;
+      const int b = sl.b[s], set = sl.set[s];
+      double sI = 0.0;
+      for (int k = 0; k < P.tau_I; ++k) {
+        float v[SPL];
+        il_load<SPL>(a.ring + (int64_t)(k % W) * NV + il, v);
+        sI += (double)v[s];
+      }
+      const double m = (double)P.m[set];
+      const double x0_bar =
+          P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)b * P.K + P.tau_I - 1] : 0.0) - (double)sb[s];
+      const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, sl.strm[s]).x);
+      double y0, dy0;
+      relaxed_init((double)P.i0[set], u, P.tau, y0, dy0);
+      const double v = x0_bar * dy0;
+      if (v != 0.0) atomicAdd(&s_gi0[b], v);
+    }
+  }
+  if (__ballot(gnz) != 0ull && lane == 0) atomicOr(&a.gz_next[r >> 6], 1ull << (r & 63));
+}
+
+template <int SPL, bool ANY_LDS>
+__global__ void __launch_bounds__(kBBlock, 4) k_bbwd64(BBwdArgs a) {
+  extern __shared__ unsigned long long lds[];
+  const int tid = threadIdx.x;
+  const DGraph& G = a.G;
+  const DParams& P = a.P;
+  const BSims& S = a.S;
+  unsigned long long* s_any = lds;
+  double* s_gS = (double*)(lds + (ANY_LDS ? a.any_words : 0));  // [B][n_age] sum of lam_bar * A / Z
+  double* s_gi0 = s_gS + (int64_t)S.B * P.n_age;                 // [B]
+  for (int x = tid; x < S.B * (P.n_age + 1); x += kBBlock) s_gS[x] = 0.0;
+  if (ANY_LDS && a.do_gather)
+    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.gz_cur[x];
+  for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
+    a.gz_clr[x] = 0ull;
+  __syncthreads();
+  const int lane = tid & 63;
+  const Slots<SPL> sl = lane_slots<SPL>(S, lane);
+  const int64_t NV = (int64_t)G.N * 64 * SPL;
+  const __amdgpu_buffer_rsrc_t rg = rsrc(a.g_cur, NV * 4);
+  double acc[SPL];
+
+  for (;;) {
+    const int tile = next_tile(a.work, lane, 0, 64);
+    if (tile >= G.n_btiles) break;
+    const TileInfo ti = G.btiles[tile];
+    int open = ti.r0 - 1;
+#pragma unroll
+    for (int s = 0; s < SPL; ++s) acc[s] = 0.0;
+    for (int64_t wb = ti.e0;; wb += 64) {
+      const bool fin = wb >= ti.e1;
+      const int nwin = fin ? 0 : (int)(ti.e1 - wb < 64 ? ti.e1 - wb : 64);
+      const bool okc = lane < nwin;
+      const int64_t pos = okc ? wb + lane : ti.e0;
+      const uint32_t pk = okc ? G.colp[pos] : 0u;
+      const float wl = okc ? G.wp[pos] : 0.f;
+      const uint32_t c = pk & 0xFFFFFFu;
+      int adv = (int)(pk >> 24);
+      if (lane == 0) {
+        if (fin) adv = ti.r1 - open;
+        else if (wb == ti.e0) adv -= ti.pad0;
+      }
+      const bool need = a.do_gather && okc && any_bit<ANY_LDS>(s_any, a.gz_cur, c);
+      const unsigned long long rs = __ballot(adv > 0);
+      const unsigned long long nd = __ballot(need);
+      // row segments of the window: [k0, next row start)
+      int k0 = 0;
+      for (;;) {
+        if ((rs >> k0) & 1ull) {
+          for (int na = __builtin_amdgcn_readlane(adv, k0); na > 0; --na) {
+            if (open >= ti.r0) bwd_agent64<SPL>(a, sl, lane, open, acc, NV, s_gS, s_gi0);
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) acc[s] = 0.0;
+            ++open;
+          }
+        }
+        const unsigned long long after = k0 < 63 ? (rs >> (k0 + 1)) << (k0 + 1) : 0ull;
+        const int k1 = after ? __builtin_ctzll(after) : 64;
+        unsigned long long act = nd & (k1 < 64 ? ((1ull << k1) - 1ull) : ~0ull) & ~((1ull << k0) - 1ull);
+        while (act) {
+          uint32_t off[kBGather];
+          float wk[kBGather];
+#pragma unroll
+          for (int u = 0; u < kBGather; ++u) {
+            off[u] = kOut;
+            wk[u] = 0.f;
+            if (act) {
+              const int k = __builtin_ctzll(act);
+              act &= act - 1ull;
+              const uint32_t ck = (uint32_t)__builtin_amdgcn_readlane((int)c, k);
+              off[u] = (uint32_t)il_index<SPL>(ck, lane, 0) * 4u;
+              wk[u] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wl), k));
+            }
+          }
+          float gv[kBGather][SPL];
+#pragma unroll
+          for (int u = 0; u < kBGather; ++u) il_rload<SPL>(rg, off[u], gv[u]);
+#pragma unroll
+          for (int u = 0; u < kBGather; ++u)
+#pragma unroll
+            for (int s = 0; s < SPL; ++s) acc[s] += (double)wk[u] * (double)gv[u][s];
+        }
+        if (k1 >= 64) break;
+        k0 = k1;
+      }
+      if (fin) break;
+    }
+  }
+  __syncthreads();
+  const int slot = blockIdx.x & (kSlots - 1);
+  if (a.t >= 1) {
+    const int d = a.t - 1;
+    for (int x = tid; x < S.B * P.n_age; x += kBBlock) {
+      const double v = s_gS[x];
+      if (v != 0.0) {
+        const int set = (x / P.n_age) % S.n_sets, g = x % P.n_age;
+        atomicAdd(&a.gS[((int64_t)set * P.n_age + g) * kSlots + slot], v * (double)P.R[set * P.K + d]);
+      }
+    }
+    for (int b = tid; b < S.B; b += kBBlock) {
+      const int set = b % S.n_sets;
+      double sum = 0.0;
+      for (int g = 0; g < P.n_age; ++g) sum += s_gS[b * P.n_age + g] * (double)P.S[set * P.n_age + g];
+      if (sum != 0.0) atomicAdd(&a.gR[((int64_t)set * P.K + d) * kSlots + slot], sum);
+    }
+  } else {
+    for (int b = tid; b < S.B; b += kBBlock) {
+      const double v = s_gi0[b];
+      if (v != 0.0) atomicAdd(&a.gi0[(int64_t)(b % S.n_sets) * kSlots + slot], v);
+    }
+  }
+}
+
 template __global__ void k_binit<1>(BInitArgs);
 template __global__ void k_binit<2>(BInitArgs);
 template __global__ void k_binit<4>(BInitArgs);
@@ -443,6 +825,18 @@ template __global__ void k_bfwd<4, true>(BFwdArgs);
 template __global__ void k_bfwd<1, false>(BFwdArgs);
 template __global__ void k_bfwd<2, false>(BFwdArgs);
 template __global__ void k_bfwd<4, false>(BFwdArgs);
+template __global__ void k_bfwd64<1, true>(BFwdArgs);
+template __global__ void k_bfwd64<2, true>(BFwdArgs);
+template __global__ void k_bfwd64<4, true>(BFwdArgs);
+template __global__ void k_bfwd64<1, false>(BFwdArgs);
+template __global__ void k_bfwd64<2, false>(BFwdArgs);
+template __global__ void k_bfwd64<4, false>(BFwdArgs);
+template __global__ void k_bbwd64<1, true>(BBwdArgs);
+template __global__ void k_bbwd64<2, true>(BBwdArgs);
+template __global__ void k_bbwd64<4, true>(BBwdArgs);
+template __global__ void k_bbwd64<1, false>(BBwdArgs);
+template __global__ void k_bbwd64<2, false>(BBwdArgs);
+template __global__ void k_bbwd64<4, false>(BBwdArgs);
 template __global__ void k_bbwd<1, true>(BBwdArgs);
 template __global__ void k_bbwd<2, true>(BBwdArgs);
 template __global__ void k_bbwd<4, true>(BBwdArgs);

@@ -393,7 +393,10 @@ static gabm_status check_run(const Graph& G, const gabm_params* p, const gabm_ru
     GABM_CHECK(run->precision == GABM_F32, GABM_EUNSUPPORTED, "batched runs store float state");
     GABM_CHECK(G.er_off_h.empty() || G.er_off_h.back() == 0, GABM_EUNSUPPORTED,
                "batched runs take static contact layers only (no daily random layer)");
-    GABM_CHECK((int64_t)G.N * B <= ((int64_t)1 << 29), GABM_EUNSUPPORTED, "a batched run needs N * B <= 2^29");
+    // per-simulation vectors may be padded to 64 lanes x (1, 2 or 4) simulations per agent
+    const int64_t padded = B > 32 ? 64 * (B <= 64 ? 1 : (B <= 128 ? 2 : 4)) : B;
+    GABM_CHECK((int64_t)G.N * padded <= ((int64_t)1 << 29), GABM_EUNSUPPORTED,
+               "a batched run needs N * B <= 2^29 (B rounded up to 64, 128 or 256 above 32)");
   }
   return GABM_OK;
 }

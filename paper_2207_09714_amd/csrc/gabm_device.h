@@ -99,7 +99,8 @@ __device__ __forceinline__ uint32_t make_rec(uint32_t st, uint32_t tm, int eday)
 // Kernel-argument views.
 
 // One receiver tile: rows [r0, r1), contacts [e0, e1); 32 bytes, read with
-// two independent 16-byte loads.
+// two independent 16-byte loads.  In the batched tile table, pad0 counts the
+// (empty) rows of earlier tiles that also start at contact e0.
 struct alignas(16) TileInfo {
   int64_t e0, e1;
   int32_t r0, r1, pad0, pad1;

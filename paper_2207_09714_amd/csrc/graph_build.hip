@@ -474,7 +474,10 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
       fi[k].r1 = ft[k + 1];
       fi[k].e0 = rp[ft[k]];
       fi[k].e1 = rp[ft[k + 1]];
-      fi[k].pad0 = fi[k].pad1 = 0;
+      // rows of earlier tiles that start (empty) at this tile's first contact
+      const int64_t first = std::lower_bound(rp.begin(), rp.begin() + ft[k], fi[k].e0) - rp.begin();
+      fi[k].pad0 = (int32_t)(ft[k] - first);
+      fi[k].pad1 = 0;
     }
     GABM_HIP(dalloc(&G.btiles, fi.size()));
     GABM_HIP(hipMemcpyAsync(G.btiles, fi.data(), sizeof(TileInfo) * fi.size(), hipMemcpyHostToDevice, st));

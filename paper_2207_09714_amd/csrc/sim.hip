@@ -94,10 +94,11 @@ struct Layout {
   }
 };
 
-static Layout layout(const Graph& G, int B, int n_out, int n_sets, int K, int W, int ckpt, int n_seg, int mode,
-                     size_t rsz, bool has_er, int64_t mask_words) {
+static Layout layout(const Graph& G, int B, int64_t NVs, int n_out, int n_sets, int K, int W, int ckpt, int n_seg,
+                     int mode, size_t rsz, bool has_er, int64_t mask_words) {
   Layout L{};
   const size_t NB = (size_t)G.N * B;
+  const size_t NV = (size_t)NVs;
   const bool soft = mode == GABM_SOFT;
   L.rec = NB * 4;
   L.mask = soft ? 0 : (size_t)mask_words * 8;
@@ -105,8 +106,8 @@ static Layout layout(const Graph& G, int B, int n_out, int n_sets, int K, int W,
   L.soft_vec = soft ? NB * rsz : 0;
   L.soft_ring = soft ? (size_t)W * NB * rsz : 0;
   const bool diff = mode != GABM_PLAIN;
-  L.st_A = diff ? (size_t)ckpt * NB * rsz : 0;
-  L.st_fl = (diff && !soft) ? (size_t)ckpt * NB : 0;
+  L.st_A = diff ? (size_t)ckpt * NV * rsz : 0;
+  L.st_fl = (diff && !soft) ? (size_t)ckpt * NV : 0;
   L.st_S = (diff && soft) ? (size_t)ckpt * NB * rsz : 0;
   const size_t nck = (diff && n_seg > 1) ? (size_t)n_seg : 0;
   L.ck_rec = soft ? 0 : nck * NB * 4;
@@ -114,9 +115,9 @@ static Layout layout(const Graph& G, int B, int n_out, int n_sets, int K, int W,
   L.cnt = (size_t)n_out * K * kSlots * kCnt * 8;
   L.cnt0 = (size_t)n_out * kSlots * kCnt * 8;
   L.drm = (size_t)n_out * K * 8;
-  L.ring = diff ? (size_t)W * NB * rsz : 0;
-  L.sbar = diff ? NB * rsz : 0;
-  L.g = diff ? NB * rsz : 0;
+  L.ring = diff ? (size_t)W * NV * rsz : 0;
+  L.sbar = diff ? NV * rsz : 0;
+  L.g = diff ? NV * rsz : 0;
   L.ier = (diff && has_er) ? NB * 8 : 0;
   L.gR = (size_t)n_sets * K * kSlots * 8;
   L.gS = (size_t)n_sets * G.n_age * kSlots * 8;
@@ -170,6 +171,7 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
   s.fast_bwd_ok = fast_shape && s.mode == GABM_HARD_ST;
   s.rsz = run->precision == GABM_F64 ? 8 : 4;
   s.NB = (int64_t)G.N * s.B;
+  s.NV = s.NB;
   if (s.B == 1) {
     s.bw = 0;
     s.mask_words = G.N / 64 + 2;
@@ -180,6 +182,8 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
     s.spl = s.B <= 64 ? 1 : (s.B <= 128 ? 2 : 4);
     s.any_words = (int64_t)G.N / 64 + 2;
     s.b_any_lds = s.any_words <= kBAnyLdsWords;
+    s.b_wide = s.LB == 64 && G.n_chunks > 0;
+    if (s.b_wide) s.NV = (int64_t)G.N * 64 * s.spl;
   }
   s.gz_bytes = 0;
   if (s.fast_bwd_ok) s.gz_bytes = (size_t)s.mask_words * 8;
@@ -189,7 +193,7 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
 gabm_status sim_workspace(const Graph& G, const gabm_params* p, const gabm_run_desc* run, size_t* bytes) {
   Sim s;
   sim_shape(s, G, p, run);
-  Layout L = layout(G, s.B, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz,
+  Layout L = layout(G, s.B, s.NV, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz,
                     G.er_off_h.back() > 0, s.mask_words);
   *bytes = L.total() + extra_bytes(s);
   return GABM_OK;
@@ -211,11 +215,11 @@ static void batched_grids(Sim& s) {
   const size_t lb = bbwd_lds(s.B, s.n_age, s.any_words, s.b_any_lds);
   s.bgrid_i = resident_grid(k_binit<SPL>, 0, s.n_cu);
   if (s.b_any_lds) {
-    s.bgrid_f = resident_grid(k_bfwd<SPL, true>, lf, s.n_cu);
-    s.bgrid_b = resident_grid(k_bbwd<SPL, true>, lb, s.n_cu);
+    s.bgrid_f = s.b_wide ? resident_grid(k_bfwd64<SPL, true>, lf, s.n_cu) : resident_grid(k_bfwd<SPL, true>, lf, s.n_cu);
+    s.bgrid_b = s.b_wide ? resident_grid(k_bbwd64<SPL, true>, lb, s.n_cu) : resident_grid(k_bbwd<SPL, true>, lb, s.n_cu);
   } else {
-    s.bgrid_f = resident_grid(k_bfwd<SPL, false>, lf, s.n_cu);
-    s.bgrid_b = resident_grid(k_bbwd<SPL, false>, lb, s.n_cu);
+    s.bgrid_f = s.b_wide ? resident_grid(k_bfwd64<SPL, false>, lf, s.n_cu) : resident_grid(k_bfwd<SPL, false>, lf, s.n_cu);
+    s.bgrid_b = s.b_wide ? resident_grid(k_bbwd64<SPL, false>, lb, s.n_cu) : resident_grid(k_bbwd<SPL, false>, lb, s.n_cu);
   }
 }
 
@@ -230,7 +234,7 @@ static gabm_status batched_setup(Sim& s) {
 gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc* run, Sim& s) {
   sim_shape(s, G, p, run);
   const bool has_er = G.er_off_h.back() > 0;
-  Layout L = layout(G, s.B, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz, has_er, s.mask_words);
+  Layout L = layout(G, s.B, s.NV, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz, has_er, s.mask_words);
   auto al = [&](void** ptr, size_t n) -> gabm_status {
     if (n == 0) {
       *ptr = nullptr;
@@ -319,7 +323,7 @@ static Rng make_rng(const gabm_rng* r) {
 
 template <typename RT>
 static RT* store_ptr(void* base, const Sim& s, int slot) {
-  return base ? (RT*)base + (int64_t)slot * s.NB : nullptr;
+  return base ? (RT*)base + (int64_t)slot * s.NV : nullptr;
 }
 
 // B = 1 path ------------------------------------------------------------------
@@ -379,7 +383,7 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.Sv = (RT*)s.Sv; a.x0 = (const RT*)s.x0; a.ring = (RT*)s.xi_ring;
   const bool store = slot >= 0 && s.mode != GABM_PLAIN;
   a.A_st = store ? store_ptr<RT>(s.A_st, s, slot) : nullptr;
-  a.fl_st = (store && !soft) ? s.fl_st + (int64_t)slot * s.NB : nullptr;
+  a.fl_st = (store && !soft) ? s.fl_st + (int64_t)slot * s.NV : nullptr;
   a.S_st = (store && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.cnt = count ? s.cnt : nullptr;
   a.lam_out = nullptr;
@@ -469,7 +473,7 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.infbar_er = (gather && has_er) ? s.infbar_er : nullptr;
   a.ring = (RT*)s.ring; a.Sbar = (RT*)s.Sbar;
   a.A_st = t >= 1 ? store_ptr<RT>(s.A_st, s, slot) : nullptr;
-  a.fl_st = (t >= 1 && !soft) ? s.fl_st + (int64_t)slot * s.NB : nullptr;
+  a.fl_st = (t >= 1 && !soft) ? s.fl_st + (int64_t)slot * s.NV : nullptr;
   a.S_st = (t >= 1 && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.Dbar = s.Dbar_eff; a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
   if (std::is_same<RT, float>::value && s.fast_bwd_ok) {
@@ -533,15 +537,27 @@ static void bt_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStrea
 template <int SPL>
 static void bt_launch_fwd(Sim& s, const BFwdArgs& a, hipStream_t st) {
   const size_t lds = bfwd_lds(s.B, s.any_words, s.b_any_lds);
-  if (s.b_any_lds) hipLaunchKernelGGL((k_bfwd<SPL, true>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
-  else hipLaunchKernelGGL((k_bfwd<SPL, false>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+  if (s.b_wide) {
+    if (s.b_any_lds) hipLaunchKernelGGL((k_bfwd64<SPL, true>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+    else hipLaunchKernelGGL((k_bfwd64<SPL, false>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+  } else if (s.b_any_lds) {
+    hipLaunchKernelGGL((k_bfwd<SPL, true>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_bfwd<SPL, false>), dim3(s.bgrid_f), dim3(kBBlock), lds, st, a);
+  }
 }
 
 template <int SPL>
 static void bt_launch_bwd(Sim& s, const BBwdArgs& a, hipStream_t st) {
   const size_t lds = bbwd_lds(s.B, s.n_age, s.any_words, s.b_any_lds);
-  if (s.b_any_lds) hipLaunchKernelGGL((k_bbwd<SPL, true>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
-  else hipLaunchKernelGGL((k_bbwd<SPL, false>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+  if (s.b_wide) {
+    if (s.b_any_lds) hipLaunchKernelGGL((k_bbwd64<SPL, true>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+    else hipLaunchKernelGGL((k_bbwd64<SPL, false>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+  } else if (s.b_any_lds) {
+    hipLaunchKernelGGL((k_bbwd<SPL, true>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+  } else {
+    hipLaunchKernelGGL((k_bbwd<SPL, false>), dim3(s.bgrid_b), dim3(kBBlock), lds, st, a);
+  }
 }
 
 // one forward day of all simulations; `replay` = recomputation inside the reverse pass
@@ -561,8 +577,8 @@ static void bt_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.any_clr = s.anyI[(t + 2) % 3];
   a.any_words = s.any_words;
   const bool store = slot >= 0 && s.mode != GABM_PLAIN;
-  a.A_st = store ? (float*)s.A_st + (int64_t)slot * s.NB : nullptr;
-  a.fl_st = store ? s.fl_st + (int64_t)slot * s.NB : nullptr;
+  a.A_st = store ? (float*)s.A_st + (int64_t)slot * s.NV : nullptr;
+  a.fl_st = store ? s.fl_st + (int64_t)slot * s.NV : nullptr;
   a.cnt = count ? s.cnt : nullptr;
   a.work = s.wq + (replay ? s.K + t : t);
   KTime kt(s, st, GABM_KT_DAY_FWD);
@@ -595,8 +611,8 @@ static void bt_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.g_prev = (float*)s.g[(t + 1) & 1];
   a.ring = (float*)s.ring;
   a.Sbar = (float*)s.Sbar;
-  a.A_st = t >= 1 ? (const float*)s.A_st + (int64_t)slot * s.NB : nullptr;
-  a.fl_st = t >= 1 ? s.fl_st + (int64_t)slot * s.NB : nullptr;
+  a.A_st = t >= 1 ? (const float*)s.A_st + (int64_t)slot * s.NV : nullptr;
+  a.fl_st = t >= 1 ? s.fl_st + (int64_t)slot * s.NV : nullptr;
   a.Dbar = s.Dbar_eff;
   a.gz_cur = s.gz[t % 3];
   a.gz_next = s.gz[(t + 2) % 3];
@@ -614,8 +630,8 @@ static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st
   const int64_t n = (int64_t)sim_n_out(s) * s.K;
   hipLaunchKernelGGL(k_dbar_eff, dim3(blocks_capped(n)), dim3(kBlock), 0, st, sim_n_out(s), s.K, s.Dbar, lw, db,
                      s.Dbar_eff);
-  fill0(s.ring, (size_t)s.W * s.NB * s.rsz, st);
-  fill0(s.Sbar, s.NB * s.rsz, st);
+  fill0(s.ring, (size_t)s.W * s.NV * s.rsz, st);
+  fill0(s.Sbar, s.NV * s.rsz, st);
   fill0(s.infbar_er, s.infbar_er ? (size_t)s.NB * 8 : 0, st);
   for (int k = 0; k < 3; ++k) fill0(s.gz[k], s.gz_bytes, st);
   if (s.wq) fill0(s.wq + s.K, (size_t)(2 * s.K + 1) * 4, st);  // counters of replayed days and reverse steps

@@ -18,6 +18,7 @@ struct Sim {
   int32_t use_graph = 0;
   size_t rsz = 4;        // bytes of one stored real
   int64_t NB = 0;        // N * B
+  int64_t NV = 0;        // entries of one per-simulation vector: N * B, or N * 64 * SPL lane-interleaved (B > 32)
   int64_t mask_words = 0;  // 64-bit words per mask buffer
   int32_t bw = 1;        // 32-bit mask words per agent (batched), 0 for B = 1 bit-packed layout
 
@@ -77,6 +78,7 @@ struct Sim {
   int32_t LB = 64, spl = 1, indep = 0;
   int64_t any_words = 0;
   bool b_any_lds = true;
+  bool b_wide = false;  // B > 32 with the packed contact form: one wave per tile, 64-contact windows
   unsigned long long* anyI[3] = {nullptr, nullptr, nullptr};
   unsigned int* wq = nullptr;  // [3K+1]: forward days, replayed days, reverse steps
   int bgrid_i = 0, bgrid_f = 0, bgrid_b = 0;

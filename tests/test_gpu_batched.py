@@ -149,8 +149,9 @@ def test_batched_two_lanes_per_simulation_gradients(G, O):
         assert_grads(got, want)
 
 
-def test_batched_checkpoint_and_hip_graph_invariance(G):
-    wl = make_workload("c4a", n_agents=4000, K=18, n_sets=8, n_reps=2)
+@pytest.mark.parametrize("n_sets,n_reps", [(8, 2), (20, 2)])
+def test_batched_checkpoint_and_hip_graph_invariance(G, n_sets, n_reps):
+    wl = make_workload("c4a", n_agents=4000, K=18, n_sets=n_sets, n_reps=n_reps)
     tgt = np.linspace(0.0, 0.8, wl.K)
     _say("batched checkpoint interval and hipGraph capture")
     g = graph_of(G, wl)
@@ -167,8 +168,9 @@ def test_batched_checkpoint_and_hip_graph_invariance(G):
     assert np.allclose(gr["dR"].cpu().numpy(), a["dR"], rtol=1e-10, atol=1e-14)
 
 
-def test_batched_day_level_entry_points(G):
-    wl = make_workload("c4a", n_agents=2000, K=10, n_sets=4, n_reps=2)
+@pytest.mark.parametrize("n_sets,n_reps", [(4, 2), (17, 4)])
+def test_batched_day_level_entry_points(G, n_sets, n_reps):
+    wl = make_workload("c4a", n_agents=2000, K=10, n_sets=n_sets, n_reps=n_reps)
     tgt = torch.tensor(np.linspace(0.0, 0.3, wl.K), device="cuda")
     _say("batched day-level entry points")
     g = graph_of(G, wl)
