@@ -219,9 +219,11 @@ typedef struct {
                           many days, recomputing each segment from a state snapshot; 0 = keep all */
   int32_t precision;   /* GABM_F32 or GABM_F64 storage */
   int32_t use_hip_graph; /* capture each forward segment / backward day loop in a hipGraph */
-  int32_t schedule;    /* 0: choose per simulation (persistent LDS-mask kernels when eligible:
-                          float state, one parameter set and population, up to 2^20 agents);
-                          1: receiver-tile kernels only */
+  int32_t schedule;    /* 0: choose per simulation (B = 1: persistent LDS-mask kernels when
+                          eligible: float state, one parameter set and population, up to 2^20
+                          agents; B > 32: one wave per tile with 64-contact windows);
+                          1: receiver-tile kernels (B = 1) / lane-group kernels (B > 1) only.
+                          gabm_autotune picks between them by measurement. */
   int32_t time_kernels; /* record HIP events around every fused day kernel (eager launches only) */
 } gabm_run_desc;
 
@@ -313,6 +315,18 @@ typedef struct {
 } gabm_kernel_times;
 
 gabm_status gabm_sim_kernel_times(gabm_sim s, gabm_kernel_times *out, int32_t reset);
+
+/* Autotuner for the kernel schedule (gabm_run_desc.schedule): for every
+ * schedule of this build (GABM_N_SCHEDULES), creates a temporary simulation
+ * of the run (p, run) with that schedule, times `days` forward days of it on
+ * `stream` (HIP events, after a warm-up day), and returns in *best a copy of
+ * *run with the fastest schedule.  ms_per_day (host, GABM_N_SCHEDULES
+ * entries, may be NULL) receives the measured times.  Allocates and frees
+ * the temporary workspaces (hipMalloc); synchronises with `stream`.  days
+ * must be in [1, K].  The parameters in p are only read. */
+#define GABM_N_SCHEDULES 2
+gabm_status gabm_autotune(gabm_graph g, const gabm_params *p, const gabm_run_desc *run, const gabm_rng *rng,
+                          int32_t days, gabm_run_desc *best, double *ms_per_day, void *stream);
 
 gabm_status gabm_sim_destroy(gabm_sim s);
 

@@ -26,8 +26,9 @@ EXPORTS = (
     "gabm_transmit_fwd", "gabm_sample_infect", "gabm_progress_stages", "gabm_transmit_bwd",
     "gabm_param_grad_reduce", "gabm_er_daily", "gabm_sim_create", "gabm_sim_workspace_size", "gabm_sim_forward",
     "gabm_sim_backward", "gabm_day_fwd", "gabm_day_bwd", "gabm_sim_records", "gabm_sim_kernel_times",
-    "gabm_sim_destroy",
+    "gabm_sim_destroy", "gabm_autotune",
 )
+N_SCHEDULES = 2
 
 
 class GabmError(RuntimeError):
@@ -114,6 +115,8 @@ def lib() -> C.CDLL:
         "gabm_sim_records": ([vp, C.POINTER(vp)], C.c_int),
         "gabm_sim_kernel_times": ([vp, C.POINTER(KernelTimes), i32], C.c_int),
         "gabm_sim_destroy": ([vp], C.c_int),
+        "gabm_autotune": ([vp, C.POINTER(Params), C.POINTER(RunDesc), C.POINTER(Rng), i32, C.POINTER(RunDesc),
+                           C.POINTER(C.c_double), vp], C.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

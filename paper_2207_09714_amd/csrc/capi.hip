@@ -494,6 +494,63 @@ gabm_status gabm_sim_kernel_times(gabm_sim s, gabm_kernel_times* out, int32_t re
   return sim_kernel_times(s->s, out, reset);
 }
 
+gabm_status gabm_autotune(gabm_graph g, const gabm_params* p, const gabm_run_desc* run, const gabm_rng* rng,
+                          int32_t days, gabm_run_desc* best, double* ms_per_day, void* stream) {
+  GABM_CHECK(g && best && rng, GABM_EINVAL, "graph, best or rng is NULL");
+  DParams P;
+  gabm_status rc = check_params(g->g, p, &P);
+  if (rc != GABM_OK) return rc;
+  rc = check_run(g->g, p, run);
+  if (rc != GABM_OK) return rc;
+  GABM_CHECK(days >= 1 && days <= p->K, GABM_ERANGE, "days outside [1, K]");
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  GABM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    set_error("hipEventCreate failed");
+    return GABM_EHIP;
+  }
+  int best_sched = 0;
+  float best_ms = 0.f;
+  for (int sched = 0; sched < GABM_N_SCHEDULES && rc == GABM_OK; ++sched) {
+    gabm_run_desc r = *run;
+    r.schedule = sched;
+    r.use_hip_graph = 0;
+    r.time_kernels = 0;
+    Sim* s = new (std::nothrow) Sim();
+    if (!s) {
+      set_error("host allocation failed");
+      rc = GABM_ENOMEM;
+      break;
+    }
+    rc = sim_create(g->g, p, &r, *s);
+    if (rc == GABM_OK) rc = sim_day_fwd(*s, P, rng, 0, nullptr, 0, nullptr, st);  // warm-up
+    float ms = 0.f;
+    if (rc == GABM_OK && hipEventRecord(e0, st) != hipSuccess) rc = GABM_EHIP;
+    for (int d = 0; d < days && rc == GABM_OK; ++d) rc = sim_day_fwd(*s, P, rng, d, nullptr, 0, nullptr, st);
+    if (rc == GABM_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)) {
+      set_error("timing events failed");
+      rc = GABM_EHIP;
+    }
+    s->release();
+    delete s;
+    if (rc != GABM_OK) break;
+    if (ms_per_day) ms_per_day[sched] = ms / days;
+    if (sched == 0 || ms < best_ms) {
+      best_ms = ms;
+      best_sched = sched;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc != GABM_OK) return rc;
+  *best = *run;
+  best->schedule = best_sched;
+  return GABM_OK;
+}
+
 gabm_status gabm_sim_destroy(gabm_sim s) {
   if (!s) return GABM_OK;
   s->s.release();

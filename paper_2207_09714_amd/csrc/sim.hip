@@ -182,7 +182,7 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
     s.spl = s.B <= 64 ? 1 : (s.B <= 128 ? 2 : 4);
     s.any_words = (int64_t)G.N / 64 + 2;
     s.b_any_lds = s.any_words <= kBAnyLdsWords;
-    s.b_wide = s.LB == 64 && G.n_chunks > 0;
+    s.b_wide = s.schedule == 0 && s.LB == 64 && G.n_chunks > 0;
     if (s.b_wide) s.NV = (int64_t)G.N * 64 * s.spl;
   }
   s.gz_bytes = 0;

@@ -198,6 +198,24 @@ def er_daily(graph: Graph, pop: int, rng, day: int, stream=None):
 
 # ---------------------------------------------------------------- whole runs
 
+def autotune(graph: "Graph", *, R, S, m, i0, Z, K, n_sets=1, n_reps=1, tau_E=3, tau_I=5, mode=HARD_ST,
+             per_pop_params=False, ckpt_every=0, precision=F32, T=(0, 0, 1, 0, 0), tau_g=0.5, seed=0, days=8,
+             stream=None):
+    """gabm_autotune: time `days` forward days under every kernel schedule and
+    return (fastest schedule, milliseconds per day of each schedule)."""
+    pb = ParamBlock(R=R, S=S, m=m, i0=i0, Z=Z, K=K, n_sets=n_sets, tau_E=tau_E, tau_I=tau_I, mode=mode,
+                    per_pop_params=per_pop_params, T=T, tau_g=tau_g)
+    run = L.RunDesc()
+    run.n_reps, run.ckpt_every, run.precision, run.use_hip_graph, run.schedule, run.time_kernels = (
+        int(n_reps), int(ckpt_every), int(precision), 0, 0, 0)
+    best = L.RunDesc()
+    ms = (C.c_double * L.N_SCHEDULES)()
+    rng = make_rng(seed)
+    check(lib().gabm_autotune(graph.handle, C.byref(pb.c), C.byref(run), C.byref(rng), int(days), C.byref(best), ms,
+                              C.c_void_p(_stream(stream))))
+    return int(best.schedule), [float(x) for x in ms]
+
+
 class Simulator:
     """gabm_sim: K-day runs of n_sets x n_reps simulations on one graph."""
 

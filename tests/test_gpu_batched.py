@@ -206,3 +206,46 @@ def test_batched_unsupported_shapes_fail_cleanly(G):
         G.Simulator(g2, n_sets=2, K=wl2.K, Z=wl2.Z, mode=2)
     with pytest.raises(G.L.GabmError, match="at most 256"):
         G.Simulator(g2, n_sets=2, n_reps=129, K=wl2.K, Z=wl2.Z, mode=1)
+
+
+def test_batched_wide_and_group_kernels_agree(G):
+    # schedule 0 uses the wave-per-tile kernels for B > 32, schedule 1 the lane-group kernels
+    wl = make_workload("c4a", n_agents=2500, K=14, n_sets=36, n_reps=2)
+    tgt = torch.tensor(np.linspace(0.0, 0.4, wl.K), device="cuda")
+    _say("wide vs lane-group batched kernels, B=72")
+    g = graph_of(G, wl)
+    out = []
+    for schedule in (0, 1):
+        sim = G.Simulator(g, n_sets=wl.n_sets, n_reps=wl.n_reps, K=wl.K, Z=wl.Z, mode=1, ckpt_every=5, T=wl.T,
+                          tau_g=wl.tau_g, schedule=schedule)
+        pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+        f = sim.forward(pb, seed=wl.seed, target=tgt)
+        r = {k: v.cpu().numpy().copy() for k, v in f.items()}
+        r.update({k: v.cpu().numpy().copy() for k, v in sim.backward(pb, seed=wl.seed).items()})
+        out.append(r)
+    a, b = out
+    assert np.array_equal(a["counts"], b["counts"])
+    assert np.array_equal(a["loss"], b["loss"])
+    for k in ("dR", "dS", "dm", "di0"):
+        assert np.allclose(a[k], b[k], rtol=1e-10, atol=1e-14), k
+
+
+@pytest.mark.parametrize("n_sets,n_reps,name", [(1, 1, "c2"), (20, 2, "c4a")])
+def test_autotune_picks_a_schedule_that_matches(G, n_sets, n_reps, name):
+    if name == "c2":
+        wl = make_workload("c2", n_agents=20000, K=12)
+    else:
+        wl = make_workload("c4a", n_agents=5000, K=12, n_sets=n_sets, n_reps=n_reps)
+    _say(f"autotune {name} B={n_sets * n_reps}")
+    g = graph_of(G, wl)
+    best, ms = G.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=wl.K, n_sets=n_sets, n_reps=n_reps, mode=1,
+                          T=wl.T, tau_g=wl.tau_g, seed=wl.seed, days=4)
+    assert best in (0, 1) and len(ms) == 2 and all(x > 0 for x in ms)
+    assert ms[best] == min(ms)
+    res = []
+    for schedule in (0, best):
+        sim = G.Simulator(g, n_sets=n_sets, n_reps=n_reps, K=wl.K, Z=wl.Z, mode=1, T=wl.T, tau_g=wl.tau_g,
+                          schedule=schedule)
+        pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+        res.append(sim.forward(pb, seed=wl.seed)["counts"].cpu().numpy().copy())
+    assert np.array_equal(res[0], res[1])
