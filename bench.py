@@ -201,6 +201,22 @@ def cpu_baseline(wl, days: int):
             "host_nproc": os.cpu_count()}
 
 
+def batched_alg_bytes(kind: str, N: int, E: int, B: int, W: int, stored: bool):
+    """Algorithmic HBM bytes of one batched day launch (B simulations, one
+    graph).  Forward: packed sender 4 + weight 4 per contact, read once for all
+    simulations; per agent and simulation record read 4 + write 4, plus stored
+    rate 4 + flags 1 when kept for the reverse pass; the senders' mask words
+    (B bits per agent) once.  Reverse: contacts 8; per agent and simulation
+    window-ring write 4 + read 4W, S adjoint 8, stored rate 4 + flags 1, g
+    write 4.  The reverse pass's gather of B adjoints per contact (4 B each)
+    is cache traffic, reported separately."""
+    if kind == "day_fwd":
+        return 8.0 * E + (8.0 + (5.0 if stored else 0.0)) * N * B + N * B / 8.0
+    if kind == "day_bwd":
+        return 8.0 * E + (21.0 + 4.0 * W) * N * B
+    return None
+
+
 def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
     """The batched workload: 64 parameter sets x 2 replicates on one shared
     250,000-agent graph, 45 days, differentiable forward+backward and the plain
@@ -217,9 +233,14 @@ def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
     out = {"workload": f"c4a: {wl.n_agents} agents, {E} directed contacts per day, {K} days, "
                        f"{wl.n_sets} parameter sets x {wl.n_reps} replicates = {B} simulations on one graph",
            "n_agents": wl.n_agents, "edges_per_day": E, "days": K, "sims": B}
+    sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, n_sets=wl.n_sets,
+                                    n_reps=wl.n_reps, mode=gabm.HARD_ST, ckpt_every=wl.ckpt_every, tau_g=wl.tau_g,
+                                    seed=wl.seed, days=4)
+    out["autotune"] = {"schedule": sched, "ms_per_day": sched_ms}
     for name, mode in (("diff", gabm.HARD_ST), ("plain", gabm.PLAIN)):
         sim = gabm.Simulator(g, n_sets=wl.n_sets, n_reps=wl.n_reps, K=K, Z=wl.Z, mode=mode,
-                             ckpt_every=wl.ckpt_every, use_hip_graph=not eager, time_kernels=eager, tau_g=wl.tau_g)
+                             ckpt_every=wl.ckpt_every, use_hip_graph=not eager, time_kernels=eager, tau_g=wl.tau_g,
+                             schedule=sched)
         pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
 
         def step():
@@ -239,8 +260,17 @@ def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
         leg = {"ms_per_run": dt * 1e3, "value": E * K * B / dt, "unit": "edge-days/s", "sim_days_per_s": K * B / dt}
         if eager:
             kt = sim.kernel_times(reset=True)
-            leg["kernels"] = {k: {"launches_per_run": v["launches"] / steps, "avg_ms": v["ms"] / v["launches"]}
-                              for k, v in kt.items() if v["launches"]}
+            leg["kernels"] = {}
+            for k, v in kt.items():
+                if not v["launches"]:
+                    continue
+                avg = v["ms"] / v["launches"]
+                ab = batched_alg_bytes(k, wl.n_agents, E, B, wl.tau_E + wl.tau_I, mode != gabm.PLAIN)
+                leg["kernels"][k] = {"launches_per_run": v["launches"] / steps, "avg_ms": avg,
+                                     "alg_bytes_per_launch": ab, "alg_GBps": ab / (avg * 1e-3) / 1e9 if ab else None}
+                if k == "day_bwd":
+                    # per-simulation adjoints of each contact's sender, served by L2 / MALL
+                    leg["kernels"][k]["gather_GBps"] = 4.0 * B * E / (avg * 1e-3) / 1e9
         if mode != gabm.PLAIN:
             leg["workspace_bytes"] = sim.workspace_size()
         out[name] = leg
@@ -255,7 +285,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"])
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
-                    help="eager launches with HIP-event kernel timing, or the day loop captured in hipGraphs")
+                    help="launches one by one with HIP events around every kernel (default), or the day loops "
+                         "captured in hipGraphs (no per-kernel timing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-days", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (c4a) legs")
@@ -322,7 +353,7 @@ def main():
     ck = wl.ckpt_every
     eager = args.launch == "eager"
 
-    def timed(sim, pb, backward):
+    def timed(sim, pb, backward, timing=True):
         def step():
             sim.forward(pb, seed=wl.seed, target=tgt_t)
             if backward:
@@ -330,7 +361,7 @@ def main():
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        if eager:
+        if timing:
             sim.kernel_times(reset=True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
@@ -339,20 +370,32 @@ def main():
         return (time.perf_counter() - t0) / args.steps
 
     res = {}
+    # kernel schedule picked by the library's autotuner (a few timed forward days per schedule)
+    sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST,
+                                    ckpt_every=ck, tau_g=wl.tau_g, seed=wl.seed, days=4)
+    res["autotune"] = {"schedule": sched, "ms_per_day": sched_ms}
     if args.only in (None, "diff"):
         sim = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=not eager,
-                             time_kernels=eager, tau_g=wl.tau_g)
+                             time_kernels=eager, tau_g=wl.tau_g, schedule=sched)
         pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
-        res["diff_s"] = timed(sim, pb, True)
+        res["diff_s"] = timed(sim, pb, True, eager)
         res["kt"] = sim.kernel_times(reset=True) if eager else None
         res["loss"] = float(sim.loss[0].item())
         res["grad_R"] = float(sim.dR[0].sum().item())
         res["workspace_bytes"] = sim.workspace_size()
         del sim
+        if eager:
+            # the same runs with each forward / backward captured in a hipGraph (no per-kernel timing)
+            simg = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=True,
+                                  tau_g=wl.tau_g, schedule=sched)
+            pbg = simg.params(wl.R, wl.S, wl.m, wl.i0)
+            res["graph_s"] = timed(simg, pbg, True, False)
+            del simg
     if args.only in (None, "plain"):
-        simp = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.PLAIN, use_hip_graph=not eager, time_kernels=eager)
+        simp = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.PLAIN, use_hip_graph=not eager, time_kernels=eager,
+                              schedule=sched)
         pbp = simp.params(wl.R, wl.S, wl.m, wl.i0)
-        res["plain_s"] = timed(simp, pbp, False)
+        res["plain_s"] = timed(simp, pbp, False, eager)
         res["kt_plain"] = simp.kernel_times(reset=True) if eager else None
         del simp
 
@@ -391,7 +434,13 @@ def main():
         "loss": res["loss"],
         "workspace_bytes": res["workspace_bytes"],
         "graph_gen_s": gen_s,
+        "autotune": res["autotune"],
     }
+    if "graph_s" in res:
+        out["hipgraph_launch"] = {"ms_per_step": res["graph_s"] * 1e3, "value": edge_days / res["graph_s"],
+                                  "unit": "edge-days/s",
+                                  "note": "same fwd+bwd step with each run captured in a hipGraph; no per-kernel "
+                                          "events, so not the headline"}
     kt = res["kt"]
     if kt is not None and any(v["launches"] for v in kt.values()):
         # first pass: K forward days (the last segment stored); the reverse

@@ -374,6 +374,34 @@ def test_hip_graph_replays_match_eager(G, grad_case):
         del x
 
 
+def test_kernel_timing_counts_every_launch(G, grad_case):
+    wl, tgt = grad_case
+    hip_graph = False
+    _say("kernel timing of eager launches")
+    g = graph_of(G, wl)
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=1, ckpt_every=6, use_hip_graph=hip_graph, time_kernels=True,
+                      tau_g=wl.tau_g)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    t = torch.tensor(tgt, device="cuda")
+    ref = None
+    for rep in range(2):
+        sim.kernel_times(reset=True)
+        out = sim.forward(pb, seed=wl.seed, target=t)
+        sim.backward(pb, seed=wl.seed)
+        kt = sim.kernel_times(reset=True)
+        fwd = sum(v["launches"] for k, v in kt.items() if k in ("gather_fwd", "day_fwd"))
+        bwd = sum(v["launches"] for k, v in kt.items() if k in ("agent_bwd", "day_bwd"))
+        # K forward days, the replay of all segments but the last, K + 1 reverse steps
+        n_seg = (wl.K + 5) // 6
+        assert fwd == wl.K + (n_seg - 1) * 6, kt
+        assert bwd == wl.K + 1, kt
+        assert all(v["ms"] > 0 for v in kt.values() if v["launches"]), kt
+        counts = out["counts"].cpu().numpy().copy()
+        if ref is None:
+            ref = counts
+        assert np.array_equal(counts, ref)
+
+
 def test_autograd_function_and_deaths_adjoint(G, O, grad_case):
     wl, tgt = grad_case
     _say("autograd function")
