@@ -224,7 +224,8 @@ typedef struct {
                           agents; B > 32: one wave per tile with 64-contact windows);
                           1: receiver-tile kernels (B = 1) / lane-group kernels (B > 1) only.
                           gabm_autotune picks between them by measurement. */
-  int32_t time_kernels; /* record HIP events around every fused day kernel (eager launches only) */
+  int32_t time_kernels; /* k > 0: record HIP events around every k-th launch of each class of day
+                           kernel (eager launches only; see gabm_sim_kernel_times); 0: off */
 } gabm_run_desc;
 
 /* Creates a simulation object on a built graph for the given parameter
@@ -288,10 +289,12 @@ gabm_status gabm_day_bwd(gabm_sim s, const gabm_params *p, const gabm_rng *rng, 
 gabm_status gabm_sim_records(gabm_sim s, const gabm_rec **rec);
 
 /* Durations of the day kernels launched since the last reset, per kernel
- * class, from a pair of HIP events recorded around each launch on its launch
- * stream when the simulation was created with time_kernels = 1 and
- * use_hip_graph = 0.  Synchronises with the recorded events.  reset != 0
- * clears the record.  Classes:
+ * class, from a pair of HIP events recorded around the sampled launches (every
+ * time_kernels-th launch of each class, counted from the last reset) on their
+ * launch stream, when the simulation was created with time_kernels > 0 and
+ * use_hip_graph = 0.  ms and launches cover the timed launches only, so
+ * ms / launches is the mean duration of a launch.  Synchronises with the
+ * recorded events.  reset != 0 clears the record.  Classes:
  *   GABM_KT_GATHER_FWD  persistent neighbour sum of the forward day
  *   GABM_KT_AGENT_FWD   per-agent forward day (draw, progress, masks, counts)
  *   GABM_KT_DAY_FWD     fused tiled forward day (when the split path is not used)

@@ -36,6 +36,8 @@ struct KTime {
   int a = -1;
   KTime(Sim& s_, hipStream_t st_, int cls_) : s(s_), st(st_), cls(cls_) {
     if (!s.time_kernels || s.use_graph) return;
+    // time_kernels = k: every k-th launch of each class is bracketed
+    if (s.kt_seq[cls]++ % s.time_kernels != 0) return;
     hipEvent_t e = s.next_event();
     if (!e) return;
     a = (int)s.ev_used - 1;
@@ -64,6 +66,7 @@ gabm_status sim_kernel_times(Sim& s, gabm_kernel_times* out, int reset) {
   }
   if (reset) {
     for (auto& v : s.ev_k) v.clear();
+    for (auto& n : s.kt_seq) n = 0;
     s.ev_used = 0;
   }
   return GABM_OK;

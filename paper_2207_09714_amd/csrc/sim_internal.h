@@ -60,6 +60,7 @@ struct Sim {
   int32_t time_kernels = 0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, int>> ev_k[GABM_KT_N];  // per kernel class: indices into ev_pool
+  int64_t kt_seq[GABM_KT_N] = {};                     // launches per class since the last reset
   size_t ev_used = 0;
   hipEvent_t next_event();
 

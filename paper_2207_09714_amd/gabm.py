@@ -235,7 +235,7 @@ class Simulator:
         run = L.RunDesc()
         run.n_reps, run.ckpt_every, run.precision, run.use_hip_graph, run.schedule, run.time_kernels = (
             int(n_reps), int(ckpt_every), int(precision), 1 if use_hip_graph else 0, int(schedule),
-            1 if time_kernels else 0)
+            int(time_kernels))
         self._run = run
         h = C.c_void_p()
         check(lib().gabm_sim_create(graph.handle, C.byref(pb.c), C.byref(run), C.byref(h)))
