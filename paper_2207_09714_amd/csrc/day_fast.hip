@@ -81,6 +81,28 @@ __device__ __forceinline__ void wstage_gather(const unsigned long long* mask, __
   }
 }
 
+// DPP move of a lane value with 0 for lanes without a source (or outside the row mask)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_or0(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_or0(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// one step of the segmented scan: the lane's window (count c, open sum x)
+// combined with the window before it
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_scan_step(int& c, double& x) {
+  const int c2 = dpp_or0<CTRL, ROWS>(c);
+  const double x2 = dpp_or0<CTRL, ROWS>(x);
+  if (c == 0) x += x2;
+  c += c2;
+}
+
 template <bool BWD>
 __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned long long* mask, const WStage& s,
                                            int64_t k) {
@@ -104,18 +126,17 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
   }
   // wave scans: inclusive prefix of the counts and segmented inclusive scan
   // of x; a window of lanes holds a row start exactly when its count is
-  // non-zero, so the segment flag needs no scan of its own
+  // non-zero, so the segment flag needs no scan of its own.  DPP moves
+  // (row shifts within 16 lanes, then the broadcasts of lanes 15 and 31)
+  // keep the scan off the LDS crossbar.
   int ci = cnt;
   double xi = x;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const int c2 = __shfl_up(ci, off);
-    const double x2 = __shfl_up(xi, off);
-    if (lane >= off) {
-      if (ci == 0) xi += x2;
-      ci += c2;
-    }
-  }
+  seg_scan_step<0x111, 0xF>(ci, xi);  // row_shr:1
+  seg_scan_step<0x112, 0xF>(ci, xi);  // row_shr:2
+  seg_scan_step<0x114, 0xF>(ci, xi);  // row_shr:4
+  seg_scan_step<0x118, 0xF>(ci, xi);  // row_shr:8
+  seg_scan_step<0x142, 0xA>(ci, xi);  // row_bcast:15 into rows 1 and 3
+  seg_scan_step<0x143, 0xC>(ci, xi);  // row_bcast:31 into rows 2 and 3
   int cex = ci - cnt;
   double sx = __shfl_up(xi, 1);
   int sf = cex > 0;
