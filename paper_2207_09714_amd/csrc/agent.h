@@ -30,10 +30,13 @@ __device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uin
   const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + age], Zp = P.Z[p];
   const double lam = rate(Rt, Sa, A, Zp);
   if (lam_out) *lam_out = lam;
-  const double q = -expm1(-lam);
-  const double u = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_INFECT, (uint32_t)p, stream).x);
   HardDay o;
-  o.h = u < q;
+  o.h = false;
+  if (lam > 0.0) {  // q = 0 rejects every uniform in (0, 1): no draw needed
+    const double q = -expm1(-lam);
+    const double u = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_INFECT, (uint32_t)p, stream).x);
+    o.h = u < q;
+  }
   const uint32_t st = rec_stage(r);
   uint32_t tm = rec_timer(r);
   o.was_s = st == ST_S;

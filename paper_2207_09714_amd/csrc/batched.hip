@@ -403,7 +403,6 @@ __global__ void __launch_bounds__(kBBlock, 4) k_bfwd64(BFwdArgs a) {
   __syncthreads();
   constexpr int MW = 2 * SPL;  // mask words a lane may need (bw <= MW)
   const int lane = tid & 63;
-  const bool upper = lane >= 32;
   const Slots<SPL> sl = lane_slots<SPL>(S, lane);
   const bool withE = a.mE != nullptr;
   const int64_t mbytes = (int64_t)G.N * S.bw * 4;
@@ -464,13 +463,15 @@ __global__ void __launch_bounds__(kBBlock, 4) k_bfwd64(BFwdArgs a) {
           const double wk = (double)__builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, wl), k));
 #pragma unroll
           for (int s = 0; s < SPL; ++s) {
-            const uint32_t w0 = (uint32_t)__builtin_amdgcn_readlane((int)mi[2 * s], k);
-            const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)mi[2 * s + 1], k);
-            if ((((upper ? w1 : w0)) >> sl.bsh[s]) & 1u) aI[s] += wk;
+            // words 2s, 2s+1 of the sender are the bits of simulations lane + 64 s,
+            // i.e. a lane mask: the add runs under it
+            const uint64_t mI = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)mi[2 * s + 1], k) << 32) |
+                                (uint32_t)__builtin_amdgcn_readlane((int)mi[2 * s], k);
+            if (__builtin_amdgcn_inverse_ballot_w64(mI)) aI[s] += wk;
             if (withE) {
-              const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)me[2 * s], k);
-              const uint32_t e1 = (uint32_t)__builtin_amdgcn_readlane((int)me[2 * s + 1], k);
-              if ((((upper ? e1 : e0)) >> sl.bsh[s]) & 1u) aE[s] += wk;
+              const uint64_t mE = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)me[2 * s + 1], k) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readlane((int)me[2 * s], k);
+              if (__builtin_amdgcn_inverse_ballot_w64(mE)) aE[s] += wk;
             }
           }
         }
