@@ -72,7 +72,9 @@ struct AdjOut {
 // One agent's adjoint of day d.  sE/sI: sums of inf_bar over the E and I
 // windows after day d; Sv, h: susceptible indicator and draw of day d (hard
 // values, or the relaxed ones in SOFT mode with `soft` set).  dy/dlambda is
-// evaluated only when it can matter (S^d != 0 and A > 0).
+// evaluated only when it can matter (S^d != 0 and A > 0), in single precision
+// when LOWP is set (float-state runs; gradients only).
+template <bool LOWP = false>
 __device__ __forceinline__ AdjOut agent_adjoint(const DParams& P, Rng rng, uint32_t stream, int d, int set, int p,
                                                 uint32_t loc, int age, double A, double Sv, double h, bool soft,
                                                 double sE, double sI, double Sbar1, double drm_bar) {
@@ -81,11 +83,18 @@ __device__ __forceinline__ AdjOut agent_adjoint(const DParams& P, Rng rng, uint3
   double dydl = 0.0;
   if (soft || (Sv != 0.0 && A > 0.0)) {
     const double lam = rate(Rt, Sa, A, Zp);
-    const double q = -expm1(-lam);
     const double u = unit_u(rng_block(rng, loc, (uint32_t)d, TAG_INFECT, (uint32_t)p, stream).x);
-    double y;
-    relaxed_sample(lam, q, u, P.tau, y, dydl);
-    if (soft) h = y;
+    if (LOWP) {
+      float yf, df;
+      relaxed_sample_f((float)lam, (float)u, (float)P.tau, yf, df);
+      dydl = (double)df;
+      if (soft) h = (double)yf;
+    } else {
+      const double q = -expm1(-lam);
+      double y;
+      relaxed_sample(lam, q, u, P.tau, y, dydl);
+      if (soft) h = y;
+    }
   }
   AdjOut o;
   o.Sbar = Sbar1 + h * xi_bar;

@@ -566,7 +566,7 @@ __global__ void __launch_bounds__(kBBlock) k_bbwd(BBwdArgs a) {
             const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)b * P.K + d + W] : 0.0;
             const uint32_t fl = a.fl_st[idx];
             const double Aday = (double)a.A_st[idx];
-            const AdjOut ad = agent_adjoint(P, a.rng, sl.strm[s], d, set, p, loc, age, Aday, (double)(fl & 1u),
+            const AdjOut ad = agent_adjoint<true>(P, a.rng, sl.strm[s], d, set, p, loc, age, Aday, (double)(fl & 1u),
                                             (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
             a.Sbar[idx] = (float)ad.Sbar;
             a.g_prev[idx] = (float)ad.g;
@@ -619,7 +619,7 @@ __global__ void __launch_bounds__(kBBlock) k_bbwd(BBwdArgs a) {
 // SPL-float load per lane.  Contacts are read 64 at a time, one per lane
 // (packed sender with row starts, weight); the wave walks the window's row
 // segments, gathering up to kBGather active senders of a segment at once.
-constexpr int kBGather = 16;
+constexpr int kBGather = 8;
 
 template <int SPL>
 __device__ __forceinline__ void bwd_agent64(const BBwdArgs& a, const Slots<SPL>& sl, int lane, int r,
@@ -667,7 +667,7 @@ __device__ __forceinline__ void bwd_agent64(const BBwdArgs& a, const Slots<SPL>&
         const int b = sl.b[s], set = sl.set[s];
         const double drm_bar = (d + W < P.K) ? (double)P.m[set] * a.Dbar[(int64_t)b * P.K + d + W] : 0.0;
         const double Aday = (double)Ad[s];
-        const AdjOut ad = agent_adjoint(P, a.rng, sl.strm[s], d, set, p, loc, age, Aday, (double)(fl[s] & 1u),
+        const AdjOut ad = agent_adjoint<true>(P, a.rng, sl.strm[s], d, set, p, loc, age, Aday, (double)(fl[s] & 1u),
                                         (double)((fl[s] >> 1) & 1u), false, sE[s], sI[s], (double)sb[s], drm_bar);
         sb_new[s] = (float)ad.Sbar;
         g_new[s] = (float)ad.g;

@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
       const double drm_bar = (d + W < P.K) ? m * a.Dbar[d + W] : 0.0;
       const uint32_t fl = a.fl_st[i];
       const double Aday = (double)a.A_st[i];
-      const AdjOut ad = agent_adjoint(P, a.rng, a.stream, d, 0, 0, (uint32_t)i, age, Aday, (double)(fl & 1u),
+      const AdjOut ad = agent_adjoint<true>(P, a.rng, a.stream, d, 0, 0, (uint32_t)i, age, Aday, (double)(fl & 1u),
                                       (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
       a.Sbar[i] = (float)ad.Sbar;
       a.g_prev[i] = (float)ad.g;

@@ -8,6 +8,8 @@
 // A1-A6 of Appendix A (one-day steps; no transmission on the day of exposure;
 // no reinfection; contacts accumulate within a day, not across days) and the
 // Gumbel-softmax relaxation of Appendix B.
+#include <type_traits>
+
 #include "agent.h"
 #include "day_kernels.h"
 #include "tile.h"
@@ -398,7 +400,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           Sv = (double)(pre_fl & 1u);
           h = (double)((pre_fl >> 1) & 1u);
         }
-        const AdjOut ad = agent_adjoint(P, a.rng, a.stream, d, set, p, loc, pre_age, A, Sv, h, SOFT, sE, sI, pre_Sbar,
+        const AdjOut ad = agent_adjoint<std::is_same<RT, float>::value>(P, a.rng, a.stream, d, set, p, loc, pre_age, A, Sv, h, SOFT, sE, sI, pre_Sbar,
                                         drm_bar);
         a.Sbar[i] = (RT)ad.Sbar;
         const double lam_bar = ad.lam_bar;

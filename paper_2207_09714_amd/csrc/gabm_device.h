@@ -80,6 +80,27 @@ __device__ __forceinline__ void relaxed_sample(double lam, double q, double u, d
   dydl = exp(log_sigm(z) - log(q)) * sigm(-z) / tau;
 }
 
+// The same in single precision, for runs that store float state: the
+// derivative feeds only the reverse pass (gradients), never a hard decision.
+__device__ __forceinline__ float sigm_f(float z) {
+  if (z >= 0.f) return 1.f / (1.f + expf(-z));
+  const float e = expf(z);
+  return e / (1.f + e);
+}
+__device__ __forceinline__ float log_sigm_f(float z) { return z >= 0.f ? -log1pf(expf(-z)) : z - log1pf(expf(z)); }
+__device__ __forceinline__ void relaxed_sample_f(float lam, float u, float tau, float& y, float& dydl) {
+  const float q = -expm1f(-lam);
+  if (!(q > 0.f)) {
+    y = 0.f;
+    dydl = 0.f;
+    return;
+  }
+  const float lq = logf(q);
+  const float z = (lq + lam + (log1pf(-u) - logf(u))) / tau;
+  y = sigm_f(z);
+  dydl = expf(log_sigm_f(z) - lq) * sigm_f(-z) / tau;
+}
+
 // y0 and dy0/di0 of the relaxed initial infection
 __device__ __forceinline__ void relaxed_init(double i0, double u, double tau, double& y0, double& dy0) {
   const double z = (log(i0) - log1p(-i0) + (log1p(-u) - log(u))) / tau;
