@@ -40,6 +40,9 @@ __device__ __forceinline__ uint32_t lds_bit(const unsigned long long* m, int c) 
 // agent pass.  Waves are independent: no block barrier after the mask load.
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// neighbour-sum slot of a row that crosses a chunk boundary (a NaN payload no
+// arithmetic produces)
+constexpr long long kPieced = 0x7FF8DEAD0000C0DELL;
 // software pipeline of the persistent gather (kGatherAhead <= kStages - 2)
 constexpr int kStages = 3;
 constexpr int kGatherAhead = 1;
@@ -155,8 +158,13 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
     cex += (int)adv[j];
     const uint32_t anext = j < 3 ? adv[j + 1] : after;
     if (anext) {  // the row of contact j ends here
-      if (sf) a.out[rowbase + cex - 1] = sx;
-      else a.first_piece[k] = sx;
+      const int64_t row = rowbase + cex - 1;
+      if (sf) {
+        a.out[row] = sx;
+      } else {  // the row began in an earlier chunk: its sum is assembled from pieces
+        a.first_piece[k] = sx;
+        a.out[row] = __longlong_as_double(kPieced);
+      }
     }
   }
   if (lane == kWave - 1 && after == 0) {  // the chunk's last row continues
@@ -204,12 +212,14 @@ __global__ void __launch_bounds__(kFastBlock) k_gather_fast(GatherArgs a) {
   }
 }
 
-// neighbour sum of receiver i from the gather outputs (pieces in chunk order)
+// neighbour sum of receiver i from the gather outputs: the row's own slot,
+// unless the gather marked the row as crossing chunks (then the pieces, in
+// chunk order).  Rows without contacts keep the zero written at run start.
 __device__ __forceinline__ double gathered(const DGraph& G, const GatherArgs& ga, int i) {
+  const double v = ga.out[i];
+  if (__double_as_longlong(v) != kPieced) return v;
   const int64_t e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
-  if (e0 == e1) return 0.0;
   const int64_t kA = e0 >> kChunkShift, kB = (e1 - 1) >> kChunkShift;
-  if (kA == kB) return ga.out[i];
   double s = ga.last_piece[kA];
   for (int64_t k = kA + 1; k <= kB; ++k) s += ga.first_piece[k];
   return s;

@@ -337,6 +337,8 @@ static void b1_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStrea
   const bool soft = s.mode == GABM_SOFT;
   // the daily-layer accumulator is cleared by each day's consumer; start clean
   fill0(s.A_er, s.A_er ? (size_t)s.NB * 8 : 0, st);
+  // neighbour sums of the split path: rows without contacts are never written
+  fill0(s.Abuf, s.Abuf ? (size_t)G.N * 8 : 0, st);
   if (!soft)
     for (int k = 0; k < 3; ++k) {
       fill0(s.maskI[k], s.mask_words * 8, st);
