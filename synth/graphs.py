@@ -90,6 +90,27 @@ def workplaces(n: int, rng: np.random.Generator, coverage: float = 0.6, lo: int 
     return _clique_pairs(groups)
 
 
+def _searchsorted_right(cdf: np.ndarray, r: np.ndarray, bits: int = 22) -> np.ndarray:
+    """``np.searchsorted(cdf, r, side="right")`` for queries in [0, 1), via a
+    table of the answers at the 2^bits grid points: the answer for r in
+    [k/L, (k+1)/L) lies between the table entries k and k+1, and the few
+    cdf values in between are stepped over one at a time.  The grid points
+    and r * L are exact, so the result is identical; random queries into a
+    large cdf no longer miss the cache at every bisection step."""
+    L = 1 << bits
+    tab = np.searchsorted(cdf, np.arange(L + 1, dtype=np.float64) / L, side="right")
+    k = (r * L).astype(np.int64)
+    pos = tab[k]
+    end = tab[k + 1]
+    act = np.nonzero(pos < end)[0]
+    while len(act):
+        step = cdf[pos[act]] <= r[act]
+        act = act[step]
+        pos[act] += 1
+        act = act[pos[act] < end[act]]
+    return pos
+
+
 def chung_lu(n: int, rng: np.random.Generator, gamma: float, mean_deg: float, cap: float | None = None):
     """Chung-Lu community layer.
 
@@ -110,8 +131,8 @@ def chung_lu(n: int, rng: np.random.Generator, gamma: float, mean_deg: float, ca
     m = int(round(n * mean_deg / 2))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
-    a = np.searchsorted(cdf, rng.random(m), side="right")
-    b = np.searchsorted(cdf, rng.random(m), side="right")
+    a = _searchsorted_right(cdf, rng.random(m))
+    b = _searchsorted_right(cdf, rng.random(m))
     a = np.minimum(a, n - 1)
     b = np.minimum(b, n - 1)
     keep = a != b

@@ -102,8 +102,13 @@ def normaliser(pop: Population, dst: np.ndarray, w: np.ndarray, er_mean_deg: flo
     offs = pop.pop_offsets
     wsum = np.zeros(pop.n_pops, np.float64)
     if len(dst):
-        p_of_edge = np.searchsorted(offs, dst, side="right") - 1
-        np.add.at(wsum, p_of_edge, w.astype(np.float64))
+        # every weight is a multiple of 2^-24, so these float64 sums are exact
+        # whatever order they are formed in
+        if pop.n_pops == 1:
+            wsum[0] = np.sum(w, dtype=np.float64)
+        else:
+            p_of_edge = np.searchsorted(offs, dst, side="right") - 1
+            wsum = np.bincount(p_of_edge, weights=w.astype(np.float64), minlength=pop.n_pops)
     sizes = np.diff(offs).astype(np.float64)
     kbar = wsum / sizes + float(er_mean_deg) * float(np.float32(er_weight))
     return (tau_I * kbar).astype(np.float32)
