@@ -283,6 +283,11 @@ def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
     return out
 
 
+def note(msg: str) -> None:
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -347,9 +352,11 @@ def main():
     t_gen = time.perf_counter()
     wl = make_workload(args.workload)
     gen_s = time.perf_counter() - t_gen
+    note(f"workload {wl.name}: {wl.n_agents} agents, {wl.n_edges} contacts, generated in {gen_s:.1f} s")
     g = gabm.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, n_age=8,
                    pop_offsets=wl.pop.pop_offsets, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight)
     info = g.info()
+    note("graph built")
     N, E, K = wl.n_agents, info["n_edges"] + 2 * info["er_pairs_per_day"], wl.K
     W = wl.tau_E + wl.tau_I
     has_er = info["er_pairs_per_day"] > 0
@@ -379,6 +386,7 @@ def main():
     sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST,
                                     ckpt_every=ck, tau_g=wl.tau_g, seed=wl.seed, days=4)
     res["autotune"] = {"schedule": sched, "ms_per_day": sched_ms}
+    note(f"autotune: schedule {sched}, ms per day {sched_ms}")
     if args.only in (None, "diff"):
         sim = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=not eager,
                              time_kernels=TIME_EVERY if eager else 0, tau_g=wl.tau_g, schedule=sched)
@@ -388,6 +396,7 @@ def main():
         res["loss"] = float(sim.loss[0].item())
         res["grad_R"] = float(sim.dR[0].sum().item())
         res["workspace_bytes"] = sim.workspace_size()
+        note(f"fwd+bwd: {res['diff_s'] * 1e3:.2f} ms per step")
         del sim
         if eager:
             # the same runs with each forward / backward captured in a hipGraph (no per-kernel timing)
@@ -401,6 +410,7 @@ def main():
                               time_kernels=TIME_EVERY if eager else 0, schedule=sched)
         pbp = simp.params(wl.R, wl.S, wl.m, wl.i0)
         res["plain_s"] = timed(simp, pbp, False, eager)
+        note(f"plain forward: {res['plain_s'] * 1e3:.2f} ms per run")
         res["kt_plain"] = simp.kernel_times(reset=True) if eager else None
         del simp
 

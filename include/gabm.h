@@ -119,6 +119,11 @@ typedef struct {
   int32_t n_long_rows;   /* rows processed by a whole block */
   double weight_sum;     /* sum of stored weights */
   int64_t er_pairs_per_day; /* undirected daily pairs over all populations */
+  int32_t n_sender_slices;  /* slices of 2^20 senders in the contact stream of the
+                               single-simulation split kernels; 0 = not built
+                               (no contacts, or 2^24 agents or more) */
+  int32_t reserved0;
+  int64_t n_stream_chunks;  /* 256-contact chunks of that stream */
 } gabm_graph_stats;
 
 gabm_status gabm_graph_info(gabm_graph g, gabm_graph_stats *stats);

@@ -46,7 +46,8 @@ class GraphDesc(C.Structure):
 class GraphStats(C.Structure):
     _fields_ = [("n_agents", C.c_int32), ("n_pops", C.c_int32), ("n_age", C.c_int32), ("n_edges", C.c_int64),
                 ("max_degree", C.c_int32), ("n_tiles", C.c_int32), ("n_long_rows", C.c_int32),
-                ("weight_sum", C.c_double), ("er_pairs_per_day", C.c_int64)]
+                ("weight_sum", C.c_double), ("er_pairs_per_day", C.c_int64), ("n_sender_slices", C.c_int32),
+                ("reserved0", C.c_int32), ("n_stream_chunks", C.c_int64)]
 
 
 class Params(C.Structure):

@@ -255,6 +255,9 @@ gabm_status gabm_graph_info(gabm_graph g, gabm_graph_stats* s) {
   s->n_agents = G.N; s->n_pops = G.n_pops; s->n_age = G.n_age; s->n_edges = G.E; s->max_degree = G.max_degree;
   s->n_tiles = G.n_tiles; s->n_long_rows = G.n_long; s->weight_sum = G.weight_sum;
   s->er_pairs_per_day = G.er_off_h.back();
+  s->n_sender_slices = G.n_slices;
+  s->reserved0 = 0;
+  s->n_stream_chunks = G.slice_chunk.empty() ? 0 : G.slice_chunk.back();
   return GABM_OK;
 }
 

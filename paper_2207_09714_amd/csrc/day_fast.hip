@@ -1,15 +1,21 @@
 // Split day kernels (float state, one parameter set, one population, up to
-// 2^20 agents): a persistent neighbour-sum kernel and an element-wise agent
+// 2^24 agents): a persistent neighbour-sum kernel and an element-wise agent
 // kernel.
 //
 // Neighbour sum.  One 1024-thread block per compute unit; the gathered side
-// is a one-bit-per-agent mask held in LDS for the whole launch -- the
-// infectious mask in the forward, the mask of non-zero rate adjoints g in the
-// reverse pass -- so a gather costs an LDS read, and the reverse pass reads g
-// from memory only for senders whose bit is set.  Each wave streams its own
-// chunks of the contact list (see below), with loads software-pipelined
-// across chunks.  Sums are double-precision sums of the same float terms in
-// a fixed order.
+// is a one-bit-per-agent mask held in LDS -- the infectious mask in the
+// forward, the mask of non-zero rate adjoints g in the reverse pass -- so a
+// gather costs an LDS read, and the reverse pass reads g from memory only for
+// senders whose bit is set.  The contact list is split by sender into slices
+// of 2^20 agents, whose mask fits the LDS; each slice is its own
+// receiver-sorted stream and yields its own partial row sums, added in slice
+// order by the agent pass.  The chunks of all slices are cut into one
+// contiguous range per block; a block reloads the mask when its range enters
+// the next slice, and ranges are numbered so that the blocks of one XCD
+// share a contiguous part of the stream (and of the g vector in its L2).
+// Each wave streams its own chunks of the block's range (see below), with
+// loads software-pipelined across chunks.  Sums are double-precision sums of
+// the same float terms in a fixed order.
 //
 // Agent pass.  One thread per agent finishes the day with the per-agent
 // functions of agent.h (Section 3.1, Eq. 1-3 and Progress; the
@@ -37,12 +43,17 @@ __device__ __forceinline__ uint32_t lds_bit(const unsigned long long* m, int c) 
 // crosses a chunk boundary leaves one piece per chunk (first_piece: the part
 // of the row that began before the chunk; last_piece: the part of the
 // chunk's last row that continues after it), added in chunk order by the
-// agent pass.  Waves are independent: no block barrier after the mask load.
+// agent pass; its sum slot holds a marker with the index of the chunk where
+// it ends.  Waves are independent: no block barrier after the mask load.
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-// neighbour-sum slot of a row that crosses a chunk boundary (a NaN payload no
-// arithmetic produces)
-constexpr long long kPieced = 0x7FF8DEAD0000C0DELL;
+// neighbour-sum slot of a row that crosses a chunk boundary: a quiet NaN with
+// a tag no arithmetic produces over 44 payload bits that hold the row's last
+// chunk and the number of chunks back to its first
+constexpr long long kPiecedTag = 0x7FFDA00000000000LL;
+constexpr long long kPiecedMask = (long long)0xFFFFF00000000000ULL;
+static_assert(kPieceChunkBits + kPieceBackBits == 44, "piece marker payload");
+constexpr int kXcds = 8;  // workgroups are dispatched round-robin over the XCDs
 // software pipeline of the persistent gather (kGatherAhead <= kStages - 2)
 constexpr int kStages = 3;
 constexpr int kGatherAhead = 1;
@@ -54,16 +65,19 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 struct WStage {
   u32x4 p;   // packed senders of this lane's 4 contacts
   f32x4 w;
-  uint32_t hdr; // chunk header: rows starting before the chunk | next-chunk row start << 31
+  uint32_t hdr;  // rows starting before the chunk | next-chunk row start << 31
+  uint32_t back; // chunks back to the start of the row continuing into the chunk
   f32x4 g;   // reverse: adjoints of the senders whose mask bit is set, else 0
 };
 
-__device__ __forceinline__ void wstage_load(const DGraph& G, WStage& s, int64_t k) {
+__device__ __forceinline__ void wstage_load(const GatherArgs& a, WStage& s, int64_t k) {
   const int lane = threadIdx.x & 63;
   const int64_t base = k * kChunk + lane * 4;
-  s.p = __builtin_nontemporal_load((const u32x4*)(G.colp + base));
-  s.w = __builtin_nontemporal_load((const f32x4*)(G.wp + base));
-  s.hdr = G.chunk_row[k];
+  s.p = __builtin_nontemporal_load((const u32x4*)(a.colp + base));
+  s.w = __builtin_nontemporal_load((const f32x4*)(a.wp + base));
+  const unsigned long long h = a.chunk_hdr[k];
+  s.hdr = (uint32_t)h;
+  s.back = (uint32_t)(h >> 32);
   s.g = f32x4{0.f, 0.f, 0.f, 0.f};
 }
 
@@ -73,13 +87,13 @@ __device__ __forceinline__ void wstage_load(const DGraph& G, WStage& s, int64_t 
 // branch around the load (a branch would make the compiler wait for it at
 // once).
 template <bool BWD>
-__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, __amdgpu_buffer_rsrc_t gbuf,
-                                              WStage& s) {
+__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, uint32_t sbase,
+                                              __amdgpu_buffer_rsrc_t gbuf, WStage& s) {
   if (!BWD) return;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint32_t c = s.p[j] & 0xFFFFFFu;
-    const uint32_t off = lds_bit(mask, (int)c) ? c * 4u : 0x80000000u;
+    const uint32_t off = lds_bit(mask, (int)(c - sbase)) ? c * 4u : 0x80000000u;
     s.g[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(gbuf, off, 0, 0));
   }
 }
@@ -107,15 +121,15 @@ __device__ __forceinline__ void seg_scan_step(int& c, double& x) {
 }
 
 template <bool BWD>
-__device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned long long* mask, const WStage& s,
-                                           int64_t k) {
+__device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned long long* mask, uint32_t sbase,
+                                           double* out, const WStage& s, int64_t k) {
   const int lane = threadIdx.x & 63;
   uint32_t adv[4];
   double v[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     adv[j] = s.p[j] >> 24;
-    const int c = (int)(s.p[j] & 0xFFFFFFu);
+    const int c = (int)((s.p[j] & 0xFFFFFFu) - sbase);
     v[j] = BWD ? (double)s.w[j] * (double)s.g[j] : (lds_bit(mask, c) ? (double)s.w[j] : 0.0);
   }
   // this lane's open segment and row-start count
@@ -160,16 +174,43 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
     if (anext) {  // the row of contact j ends here
       const int64_t row = rowbase + cex - 1;
       if (sf) {
-        a.out[row] = sx;
+        out[row] = sx;
       } else {  // the row began in an earlier chunk: its sum is assembled from pieces
         a.first_piece[k] = sx;
-        a.out[row] = __longlong_as_double(kPieced);
+        out[row] = __longlong_as_double(kPiecedTag | ((long long)s.back << kPieceChunkBits) | k);
       }
     }
   }
   if (lane == kWave - 1 && after == 0) {  // the chunk's last row continues
     if (sf) a.last_piece[k] = sx;
     else a.first_piece[k] = sx;
+  }
+}
+
+// The chunks [start, end) of one slice with stride `stride` (one wave's
+// share of a block's range): kStages register stages rotate by unrolling;
+// chunk c is reduced in step c, its contacts were requested kStages - 1 steps
+// earlier and (reverse) its adjoints kGatherAhead steps earlier.
+template <bool BWD>
+__device__ __forceinline__ void gather_range(const GatherArgs& a, const unsigned long long* mask, uint32_t sbase,
+                                             __amdgpu_buffer_rsrc_t gbuf, double* out, int64_t start, int64_t end,
+                                             int stride) {
+  if (start >= end) return;
+  const int64_t mine = (end - 1 - start) / stride + 1;
+  auto chunk = [&](int64_t q) { return start + (q < mine ? q : mine - 1) * stride; };
+  WStage st[kStages];
+#pragma unroll
+  for (int j = 0; j < kStages - 1; ++j) wstage_load(a, st[j], chunk(j));
+#pragma unroll
+  for (int j = 0; j < kGatherAhead; ++j) wstage_gather<BWD>(mask, sbase, gbuf, st[j]);
+  for (int64_t q = 0; q < mine; q += kStages) {
+#pragma unroll
+    for (int j = 0; j < kStages; ++j) {
+      if (q + j >= mine) break;
+      wstage_load(a, st[(j + kStages - 1) % kStages], chunk(q + j + kStages - 1));
+      wstage_gather<BWD>(mask, sbase, gbuf, st[(j + kGatherAhead) % kStages]);
+      wave_chunk<BWD>(a, mask, sbase, out, st[j], chunk(q + j));
+    }
   }
 }
 
@@ -181,47 +222,51 @@ __global__ void __launch_bounds__(kFastBlock) k_gather_fast(GatherArgs a) {
   __shared__ unsigned long long mask[kFastMaskWords];
   const int tid = threadIdx.x;
   const DGraph& G = a.G;
-  const int words = (G.N + 63) >> 6;
-  for (int x = tid; x < words; x += kFastBlock) mask[x] = a.mask[x];
-  __syncthreads();
-  const int64_t nw = (int64_t)gridDim.x * (kFastBlock / kWave);
-  const int64_t gw = (int64_t)blockIdx.x * (kFastBlock / kWave) + (tid >> 6);
-  const int64_t nch = G.n_chunks;
-  if (gw >= nch) return;
+  const int nblk = gridDim.x, b = blockIdx.x;
+  const int j = (nblk % kXcds == 0) ? (b % kXcds) * (nblk / kXcds) + b / kXcds : b;
+  const int64_t C = a.slice_chunk[a.n_slices];
+  int64_t c0 = C * j / nblk;
+  const int64_t c1 = C * (j + 1) / nblk;
   // raw buffer over g (N floats): offsets at or past N * 4 read as 0
   const __amdgpu_buffer_rsrc_t gbuf =
       __builtin_amdgcn_make_buffer_rsrc((void*)a.g, (short)0, BWD ? G.N * 4 : 0, kBufferWord3);
-  const int64_t mine = (nch - 1 - gw) / nw + 1;
-  auto chunk = [&](int64_t q) { return gw + (q < mine ? q : mine - 1) * nw; };
-  // kStages register stages rotate by unrolling: chunk c is reduced in step
-  // c, its contacts were requested kStages - 1 steps earlier and (reverse)
-  // its adjoints kGatherAhead steps earlier
-  WStage st[kStages];
-#pragma unroll
-  for (int j = 0; j < kStages - 1; ++j) wstage_load(G, st[j], chunk(j));
-#pragma unroll
-  for (int j = 0; j < kGatherAhead; ++j) wstage_gather<BWD>(mask, gbuf, st[j]);
-  for (int64_t q = 0; q < mine; q += kStages) {
-#pragma unroll
-    for (int j = 0; j < kStages; ++j) {
-      if (q + j >= mine) break;
-      wstage_load(G, st[(j + kStages - 1) % kStages], chunk(q + j + kStages - 1));
-      wstage_gather<BWD>(mask, gbuf, st[(j + kGatherAhead) % kStages]);
-      wave_chunk<BWD>(a, mask, st[j], chunk(q + j));
-    }
+  int p = 0;
+  while (p + 1 < a.n_slices && a.slice_chunk[p + 1] <= c0) ++p;
+  bool first = true;
+  while (c0 < c1) {  // block-uniform: every wave takes each barrier
+    const int64_t e = min(c1, a.slice_chunk[p + 1]);
+    const uint32_t sbase = (uint32_t)p << kSliceShift;
+    const int words = (int)min((int64_t)kFastMaskWords, ((int64_t)G.N - sbase + 63) >> 6);
+    if (!first) __syncthreads();  // every wave is done with the previous slice's mask
+    for (int x = tid; x < words; x += kFastBlock) mask[x] = a.mask[(sbase >> 6) + x];
+    __syncthreads();
+    first = false;
+    gather_range<BWD>(a, mask, sbase, gbuf, a.out + (int64_t)p * G.N, c0 + (tid >> 6), e, kFastBlock / kWave);
+    c0 = e;
+    ++p;
   }
 }
 
-// neighbour sum of receiver i from the gather outputs: the row's own slot,
-// unless the gather marked the row as crossing chunks (then the pieces, in
-// chunk order).  Rows without contacts keep the zero written at run start.
-__device__ __forceinline__ double gathered(const DGraph& G, const GatherArgs& ga, int i) {
-  const double v = ga.out[i];
-  if (__double_as_longlong(v) != kPieced) return v;
-  const int64_t e0 = G.row_ptr[i], e1 = G.row_ptr[i + 1];
-  const int64_t kA = e0 >> kChunkShift, kB = (e1 - 1) >> kChunkShift;
+// neighbour sum of receiver i in slice p from the gather outputs: the row's
+// own slot, unless the gather marked the row as crossing chunks (then the
+// pieces, in chunk order, from the chunk where the row starts to the chunk
+// where it ends, both read from the marker).  Rows without contacts keep the
+// zero written at run start.
+__device__ __forceinline__ double gathered_slice(const SliceSums& ga, int p, int i) {
+  const double v = ga.out[(int64_t)p * ga.N + i];
+  const long long bits = __double_as_longlong(v);
+  if ((bits & kPiecedMask) != kPiecedTag) return v;
+  const int64_t kB = bits & ((1LL << kPieceChunkBits) - 1);
+  const int64_t kA = kB - ((bits >> kPieceChunkBits) & ((1LL << kPieceBackBits) - 1));
   double s = ga.last_piece[kA];
   for (int64_t k = kA + 1; k <= kB; ++k) s += ga.first_piece[k];
+  return s;
+}
+
+// neighbour sum of receiver i: the slices' sums in slice order
+__device__ __forceinline__ double gathered(const SliceSums& ga, int i) {
+  double s = gathered_slice(ga, 0, i);
+  for (int p = 1; p < ga.n_slices; ++p) s += gathered_slice(ga, p, i);
   return s;
 }
 
@@ -229,7 +274,7 @@ __device__ __forceinline__ double gathered(const DGraph& G, const GatherArgs& ga
 
 // Forward: A = neighbour sum (+ daily random layer), draw, progress, masks of
 // day t+1, counts.
-__global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, GatherArgs ga) {
+__global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSums ga) {
   __shared__ unsigned scnt[kCnt];
   const int tid = threadIdx.x;
   if (tid < kCnt) scnt[tid] = 0u;
@@ -245,7 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, GatherAr
   uint32_t newst = 0u;
   bool removed = false;
   if (on) {
-    double A = gathered(G, ga, i) * P.TI;
+    double A = gathered(ga, i) * P.TI;
     if (a.A_er) {
       A += a.A_er[i];
       a.A_er[i] = 0.0;
@@ -283,7 +328,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, GatherAr
 // Reverse step t: record inf_bar^t (+ daily random layer) in the window ring,
 // then the adjoint of day t-1 (t >= 1) or of the initial infections (t = 0);
 // g^{t-1} and its non-zero mask for the next step's gather.
-__global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, GatherArgs ga) {
+__global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga) {
   __shared__ double sg[2 + 16];
   const int tid = threadIdx.x;
   if (tid < 18) sg[tid] = 0.0;
@@ -301,7 +346,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
   if (on) {
     double infbar = 0.0;
     if (a.do_gather) {
-      infbar = gathered(G, ga, i);
+      infbar = gathered(ga, i);
       if (a.infbar_er) {
         infbar += a.infbar_er[i];
         a.infbar_er[i] = 0.0;

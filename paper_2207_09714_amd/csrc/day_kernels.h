@@ -130,18 +130,43 @@ __global__ void k_day_bwd(BwdArgs<RT> a);
 // persistent neighbour sum over the fast tiles with an LDS-resident mask
 struct GatherArgs {
   DGraph G;
+  // sender-sliced contact stream: packed senders, weights, chunk headers
+  const uint32_t* colp;
+  const float* wp;
+  const unsigned long long* chunk_hdr;
+  int64_t slice_chunk[kMaxSlices + 1];  // first chunk of each slice; [n_slices] = chunk count
+  int32_t n_slices;
   const unsigned long long* mask;  // one bit per agent
   const float* g;                  // reverse: rate adjoints (read where the bit is set)
-  double* out;                     // [N] sums of rows inside one chunk
-  double* first_piece;             // [n_chunks]
-  double* last_piece;              // [n_chunks]
+  double* out;                     // [n_slices][N] per-slice row sums (or a piece marker)
+  double* first_piece;             // [chunks]
+  double* last_piece;              // [chunks]
   double TI;
 };
 
+// the neighbour sums as the agent pass reads them
+struct SliceSums {
+  const double* out;          // [n_slices][N]
+  const double* first_piece;  // [chunks]
+  const double* last_piece;   // [chunks]
+  int64_t N;
+  int32_t n_slices;
+};
+
+inline SliceSums slice_sums(const GatherArgs& a) {
+  SliceSums s;
+  s.out = a.out;
+  s.first_piece = a.first_piece;
+  s.last_piece = a.last_piece;
+  s.N = a.G.N;
+  s.n_slices = a.n_slices;
+  return s;
+}
+
 template <bool BWD>
 __global__ void k_gather_fast(GatherArgs a);
-__global__ void k_agent_fwd(FwdArgs<float> a, GatherArgs ga);
-__global__ void k_agent_bwd(BwdArgs<float> a, FastMasks fm, GatherArgs ga);
+__global__ void k_agent_fwd(FwdArgs<float> a, SliceSums ga);
+__global__ void k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga);
 __global__ void k_fin_fwd(FinArgs a);
 __global__ void k_dbar_eff(int n_out, int K, const double* Dbar, const double* w, const double* db, double* out);
 __global__ void k_fin_bwd(FinBwdArgs a);

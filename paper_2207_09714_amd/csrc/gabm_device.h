@@ -21,6 +21,15 @@ constexpr uint32_t kDayInit = 0xFFFFFFFFu;
 // one-bit-per-agent mask in LDS
 constexpr int kFastBlock = 1024;
 constexpr int kFastMaskWords = 16384;  // 64-bit words of LDS mask: up to 2^20 agents
+// The split B = 1 kernels read a sender-sliced copy of the contact list:
+// slice p holds the contacts whose sender lies in [p * 2^20, (p + 1) * 2^20),
+// so one slice's mask fits the LDS mask above.
+constexpr int kSliceShift = 20;
+constexpr int kMaxSlices = 16;         // senders below 2^24
+// a row crossing chunks is marked with its end chunk (kPieceChunkBits bits)
+// and the number of chunks back to its start (kPieceBackBits bits)
+constexpr int kPieceChunkBits = 27;
+constexpr int kPieceBackBits = 17;
 // receiver tiles of the batched kernels (one lane group per tile)
 constexpr int kBTileCap = 512;
 constexpr int kBTileRows = 64;

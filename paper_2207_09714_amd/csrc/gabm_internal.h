@@ -40,6 +40,14 @@ struct Graph {
   float* wp = nullptr;
   uint32_t* chunk_row = nullptr;
   int64_t n_chunks = 0;  // 0 = edge-parallel form not available
+  // sender-sliced stream of the split B = 1 kernels (packed like colp / wp,
+  // one receiver-sorted stream per slice, each starting at a chunk
+  // boundary); n_slices = 0 when not built
+  uint32_t* fcolp = nullptr;
+  float* fwp = nullptr;
+  unsigned long long* fchunk_hdr = nullptr;  // chunk headers (see the split kernels)
+  int32_t n_slices = 0;
+  std::vector<int64_t> slice_chunk;  // [n_slices + 1] first chunk of each slice; last = chunk count
   uint8_t* age = nullptr;
   uint16_t* pop_of = nullptr;
   int32_t* pop_off = nullptr;

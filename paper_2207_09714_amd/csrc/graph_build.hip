@@ -273,6 +273,129 @@ __global__ void k_pack_cols(const int32_t* col, const float* w, const unsigned i
   }
 }
 
+// ---- sender-sliced stream of the split B = 1 kernels
+//
+// Slice p of receiver row r is the part of the row (sorted by sender) whose
+// senders lie in [p << kSliceShift, (p + 1) << kSliceShift).  A row that is
+// empty in a slice is still counted by the row-start byte of the slice's next
+// contact; to keep that count below 256, an empty row whose index is a
+// multiple of 128 gets one zero-weight contact (sender = the slice's first
+// agent), which adds an exact 0 to its sum.
+
+__device__ __forceinline__ int64_t lower_col(const int32_t* col, int64_t a, int64_t b, int32_t c) {
+  while (a < b) {
+    const int64_t mid = (a + b) >> 1;
+    if (col[mid] < c) a = mid + 1; else b = mid;
+  }
+  return a;
+}
+
+constexpr int kSlicePadEvery = 128;
+
+// contacts of row r in slice p, [P][N+1] with a zero at index N of each slice
+__global__ void k_slice_count(const int64_t* row_ptr, const int32_t* col, int32_t N, int P, unsigned long long* cnt) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r <= N; r += (int64_t)gridDim.x * blockDim.x) {
+    if (r == N) {
+      for (int p = 0; p < P; ++p) cnt[(int64_t)p * (N + 1) + N] = 0ull;
+      continue;
+    }
+    const int64_t e1 = row_ptr[r + 1];
+    int64_t lo = row_ptr[r];
+    for (int p = 0; p < P; ++p) {
+      const int64_t hi = p == P - 1 ? e1 : lower_col(col, lo, e1, (p + 1) << kSliceShift);
+      unsigned long long c = (unsigned long long)(hi - lo);
+      if (c == 0 && (r % kSlicePadEvery) == 0) c = 1;
+      cnt[(int64_t)p * (N + 1) + r] = c;
+      lo = hi;
+    }
+  }
+}
+
+// copy each row's slices into the streams; count row starts per position.
+// spos: exclusive scan of the counts over [P][N+1] (slice p's own offsets are
+// spos[p][r] - spos[p][0]); cb: first chunk of each slice
+__global__ void k_slice_fill(const int64_t* row_ptr, const int32_t* col, const float* w, int32_t N, int P,
+                             const int64_t* spos, const int64_t* cb, uint32_t* fcolp, float* fwp, unsigned int* adv) {
+  for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e1 = row_ptr[r + 1];
+    int64_t lo = row_ptr[r];
+    for (int p = 0; p < P; ++p) {
+      const int64_t hi = p == P - 1 ? e1 : lower_col(col, lo, e1, (p + 1) << kSliceShift);
+      const int64_t* sp = spos + (int64_t)p * (N + 1);
+      const int64_t pos = sp[r] - sp[0], Ep = sp[N] - sp[0];
+      const int64_t dst = cb[p] * kChunk + pos;
+      if (hi > lo) {
+        for (int64_t e = lo; e < hi; ++e) {
+          fcolp[dst + (e - lo)] = (uint32_t)col[e];
+          fwp[dst + (e - lo)] = w[e];
+        }
+      } else if ((r % kSlicePadEvery) == 0) {
+        fcolp[dst] = (uint32_t)p << kSliceShift;
+        fwp[dst] = 0.f;
+      }
+      if (pos < Ep) atomicAdd(&adv[dst], 1u);
+      lo = hi;
+    }
+  }
+}
+
+// row-start byte of every position; zero-weight padding after each slice's
+// contacts up to its chunk boundary; flag if a count does not fit in 8 bits
+__global__ void k_slice_pack(const int64_t* spos, const int64_t* cb, int32_t N, int P, int64_t n_pad,
+                             const unsigned int* adv, uint32_t* fcolp, float* fwp, uint32_t* flag) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n_pad; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e >> kChunkShift;
+    int p = 0;
+    while (p + 1 < P && cb[p + 1] <= k) ++p;
+    const int64_t* sp = spos + (int64_t)p * (N + 1);
+    const int64_t local = e - cb[p] * kChunk, Ep = sp[N] - sp[0];
+    if (local < Ep) {
+      const unsigned int a = adv[e];
+      if (a > 255u) atomicOr(flag, 1u);
+      fcolp[e] |= min(a, 255u) << 24;
+    } else {
+      fcolp[e] = (uint32_t)p << kSliceShift;
+      fwp[e] = 0.f;
+    }
+  }
+}
+
+// chunk header: rows of its slice that start before it | (a row starts at
+// the contact after it) << 31 (always set for a slice's last chunk), and in
+// the high word how many chunks back the row continuing into it started
+__global__ void k_slice_chunk_row(const int64_t* spos, const int64_t* cb, int32_t N, int P, int64_t n_ch,
+                                  unsigned long long* hdr) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_ch; k += (int64_t)gridDim.x * blockDim.x) {
+    int p = 0;
+    while (p + 1 < P && cb[p + 1] <= k) ++p;
+    const int64_t* sp = spos + (int64_t)p * (N + 1);
+    const int64_t kl = k - cb[p], nk = cb[p + 1] - cb[p];
+    // rows r in [0, N] whose start (sp[r] - sp[0]) lies before position x of the slice
+    auto before = [&](int64_t x) {
+      int64_t a = 0, b = (int64_t)N + 1;
+      while (a < b) {
+        const int64_t mid = (a + b) >> 1;
+        if (sp[mid] - sp[0] < x) a = mid + 1; else b = mid;
+      }
+      return a;
+    };
+    const int64_t rows = before(kl * kChunk);
+    bool starts = true;
+    if (kl + 1 < nk) {
+      const int64_t rn = before((kl + 1) * kChunk);
+      starts = rn < N && sp[rn] - sp[0] == (kl + 1) * kChunk;
+    }
+    // the last row starting before the chunk continues into it unless a row
+    // starts at the chunk's first contact
+    int64_t back = 0;
+    if (rows > 0) {
+      const int64_t x = sp[rows - 1] - sp[0];
+      if (rows > N || sp[rows] - sp[0] != kl * kChunk) back = kl - (x >> kChunkShift);
+    }
+    hdr[k] = ((unsigned long long)back << 32) | (uint32_t)rows | (starts ? 0x80000000u : 0u);
+  }
+}
+
 __global__ void k_pop_of(const int32_t* pop_off, int n_pops, int32_t N, uint16_t* pop_of) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x)
     pop_of[i] = (uint16_t)pop_search(pop_off, n_pops, i);
@@ -292,6 +415,10 @@ void Graph::release() {
   hipFree(er_off);
   row_ptr = nullptr; col = nullptr; w = nullptr; tile_row = nullptr; tiles = nullptr; btiles = nullptr; colp = nullptr; wp = nullptr; chunk_row = nullptr;
   n_chunks = 0;
+  hipFree(fcolp); hipFree(fwp); hipFree(fchunk_hdr);
+  fcolp = nullptr; fwp = nullptr; fchunk_hdr = nullptr;
+  n_slices = 0;
+  slice_chunk.clear();
   age = nullptr; pop_of = nullptr;
   pop_off = nullptr; er_off = nullptr;
 }
@@ -330,6 +457,79 @@ static void make_tiles(const std::vector<int64_t>& rp, std::vector<int32_t>& til
     r = r1;
     tiles.push_back(r);
   }
+}
+
+// Sender-sliced stream of the split B = 1 kernels (from the sorted CSR).
+static gabm_status build_sliced_stream(Graph& G, hipStream_t st) {
+  const int32_t N = G.N;
+  const int P = (int)(((int64_t)N + (1 << kSliceShift) - 1) >> kSliceShift);
+  const int64_t n1 = (int64_t)P * (N + 1);
+  const int64_t n_tiles = (n1 + kScanTile - 1) / kScanTile;
+  unsigned long long *cnt = nullptr, *scan = nullptr, *sums = nullptr;
+  int64_t *spos = nullptr, *cb = nullptr;
+  unsigned int* adv = nullptr;
+  uint32_t* flag = nullptr;
+  auto cleanup = [&]() {
+    hipFree(cnt); hipFree(scan); hipFree(sums); hipFree(spos); hipFree(cb); hipFree(adv); hipFree(flag);
+  };
+  auto fail = [&](hipError_t e, const char* what) {
+    cleanup();
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return GABM_EHIP;
+  };
+  hipError_t e;
+  if ((e = dalloc(&cnt, n1)) != hipSuccess || (e = dalloc(&scan, n1)) != hipSuccess ||
+      (e = dalloc(&sums, n_tiles)) != hipSuccess || (e = dalloc(&spos, n1)) != hipSuccess ||
+      (e = dalloc(&cb, P + 1)) != hipSuccess || (e = dalloc(&flag, 1)) != hipSuccess)
+    return fail(e, "sliced stream: allocation");
+  hipLaunchKernelGGL(k_slice_count, dim3(grid_for((int64_t)N + 1)), dim3(kBlock), 0, st, G.row_ptr, G.col, N, P, cnt);
+  hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)n_tiles), dim3(kBlock), 0, st, cnt, n1, scan, sums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, st, sums, n_tiles);
+  hipLaunchKernelGGL(k_scan_add, dim3((unsigned)n_tiles), dim3(kBlock), 0, st, scan, n1, sums, spos, cnt);
+  std::vector<int64_t> s0(P), sN(P);
+  for (int p = 0; p < P; ++p) {
+    const int64_t* sp = spos + (int64_t)p * (N + 1);
+    if ((e = hipMemcpyAsync(&s0[p], sp, 8, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(&sN[p], sp + N, 8, hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return fail(e, "sliced stream: totals");
+  }
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "sliced stream: counts");
+  std::vector<int64_t> chunk0(P + 1, 0);
+  for (int p = 0; p < P; ++p) chunk0[p + 1] = chunk0[p] + (sN[p] - s0[p] + kChunk - 1) / kChunk;
+  const int64_t nch = chunk0[P], npad = nch * kChunk;
+  if (nch >= (int64_t(1) << kPieceChunkBits)) {  // chunk index does not fit the piece marker
+    cleanup();
+    return GABM_OK;
+  }
+  if ((e = dalloc(&adv, npad)) != hipSuccess || (e = dalloc(&G.fcolp, npad)) != hipSuccess ||
+      (e = dalloc(&G.fwp, npad)) != hipSuccess || (e = dalloc(&G.fchunk_hdr, nch)) != hipSuccess)
+    return fail(e, "sliced stream: allocation");
+  if ((e = hipMemsetAsync(adv, 0, sizeof(unsigned int) * npad, st)) != hipSuccess ||
+      (e = hipMemsetAsync(flag, 0, sizeof(uint32_t), st)) != hipSuccess ||
+      (e = hipMemcpyAsync(cb, chunk0.data(), sizeof(int64_t) * (P + 1), hipMemcpyHostToDevice, st)) != hipSuccess)
+    return fail(e, "sliced stream: set-up");
+  hipLaunchKernelGGL(k_slice_fill, dim3(grid_for(N)), dim3(kBlock), 0, st, G.row_ptr, G.col, G.w, N, P, spos, cb,
+                     G.fcolp, G.fwp, adv);
+  hipLaunchKernelGGL(k_slice_pack, dim3(grid_for(npad)), dim3(kBlock), 0, st, spos, cb, N, P, npad, adv, G.fcolp,
+                     G.fwp, flag);
+  hipLaunchKernelGGL(k_slice_chunk_row, dim3(grid_for(nch)), dim3(kBlock), 0, st, spos, cb, N, P, nch, G.fchunk_hdr);
+  uint32_t of = 0;
+  if ((e = hipMemcpyAsync(&of, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st)) != hipSuccess ||
+      (e = hipStreamSynchronize(st)) != hipSuccess || (e = hipGetLastError()) != hipSuccess)
+    return fail(e, "sliced stream: build");
+  cleanup();
+  if (of) {  // cannot happen with the padding rule; keep the tile kernels only
+    hipFree(G.fcolp);
+    hipFree(G.fwp);
+    hipFree(G.fchunk_hdr);
+    G.fcolp = nullptr;
+    G.fwp = nullptr;
+    G.fchunk_hdr = nullptr;
+    return GABM_OK;
+  }
+  G.n_slices = P;
+  G.slice_chunk = chunk0;
+  return GABM_OK;
 }
 
 gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
@@ -534,6 +734,15 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
       G.chunk_row = nullptr;
     } else {
       G.n_chunks = nch;
+    }
+  }
+  if (E > 0 && N < (1 << 24)) {
+    const gabm_status rc = build_sliced_stream(G, st);
+    if (rc != GABM_OK) {
+      hipFree(drows);
+      hipFree(gscr);
+      cleanup();
+      return rc;
     }
   }
   GABM_HIP(hipMemcpyAsync(&hflag, flag, sizeof(uint32_t), hipMemcpyDeviceToHost, st));

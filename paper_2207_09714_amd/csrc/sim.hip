@@ -132,7 +132,7 @@ static Layout layout(const Graph& G, int B, int64_t NVs, int n_out, int n_sets, 
 static size_t extra_bytes(const Sim& s) {
   const Graph& G = *s.G;
   size_t b = 3 * s.gz_bytes;
-  if (s.fast_fwd_ok || s.fast_bwd_ok) b += (size_t)G.N * 8 + (size_t)G.n_chunks * 16;
+  if (s.fast_fwd_ok || s.fast_bwd_ok) b += (size_t)G.n_slices * G.N * 8 + (size_t)G.slice_chunk.back() * 16;
   if (s.B > 1) b += 3 * (size_t)s.any_words * 8 + (size_t)(3 * s.K + 1) * 4;
   return b;
 }
@@ -167,9 +167,8 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
     s.n_cu = ncu;
   }
-  const bool fast_shape = s.schedule == 0 && s.n_cu > 0 && s.B == 1 && !s.per_pop && G.n_pops == 1 && G.n_chunks > 0 &&
-                          (int64_t)G.N <= (int64_t)kFastMaskWords * 64 && run->precision == GABM_F32 &&
-                          s.mode != GABM_SOFT;
+  const bool fast_shape = s.schedule == 0 && s.n_cu > 0 && s.B == 1 && !s.per_pop && G.n_pops == 1 &&
+                          G.n_slices > 0 && run->precision == GABM_F32 && s.mode != GABM_SOFT;
   s.fast_fwd_ok = fast_shape;
   s.fast_bwd_ok = fast_shape && s.mode == GABM_HARD_ST;
   s.rsz = run->precision == GABM_F64 ? 8 : 4;
@@ -287,8 +286,8 @@ gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc
   AL(s.gi0, L.gi0);
   for (int k = 0; k < 3; ++k) AL(s.gz[k], s.gz_bytes);
   if (s.fast_fwd_ok || s.fast_bwd_ok) {
-    AL(s.Abuf, (size_t)G.N * 8);
-    AL(s.piece, (size_t)G.n_chunks * 2 * 8);
+    AL(s.Abuf, (size_t)G.n_slices * G.N * 8);
+    AL(s.piece, (size_t)G.slice_chunk.back() * 2 * 8);
   }
   if (s.B > 1) {
     for (int k = 0; k < 3; ++k) AL(s.anyI[k], (size_t)s.any_words * 8);
@@ -331,6 +330,26 @@ static RT* store_ptr(void* base, const Sim& s, int slot) {
 
 // B = 1 path ------------------------------------------------------------------
 
+// arguments of the split kernels: the sender-sliced stream and its outputs
+static GatherArgs gather_args(const Sim& s, const DGraph& dg, const unsigned long long* mask, const float* g,
+                              double TI) {
+  const Graph& G = *s.G;
+  GatherArgs ga;
+  ga.G = dg;
+  ga.colp = G.fcolp;
+  ga.wp = G.fwp;
+  ga.chunk_hdr = G.fchunk_hdr;
+  for (int p = 0; p <= kMaxSlices; ++p) ga.slice_chunk[p] = G.slice_chunk[std::min(p, G.n_slices)];
+  ga.n_slices = G.n_slices;
+  ga.mask = mask;
+  ga.g = g;
+  ga.out = s.Abuf;
+  ga.first_piece = s.piece;
+  ga.last_piece = s.piece + G.slice_chunk.back();
+  ga.TI = TI;
+  return ga;
+}
+
 template <typename RT>
 static void b1_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStream_t st) {
   const Graph& G = *s.G;
@@ -338,7 +357,7 @@ static void b1_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStrea
   // the daily-layer accumulator is cleared by each day's consumer; start clean
   fill0(s.A_er, s.A_er ? (size_t)s.NB * 8 : 0, st);
   // neighbour sums of the split path: rows without contacts are never written
-  fill0(s.Abuf, s.Abuf ? (size_t)G.N * 8 : 0, st);
+  fill0(s.Abuf, s.Abuf ? (size_t)G.n_slices * G.N * 8 : 0, st);
   if (!soft)
     for (int k = 0; k < 3; ++k) {
       fill0(s.maskI[k], s.mask_words * 8, st);
@@ -393,15 +412,13 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.cnt = count ? s.cnt : nullptr;
   a.lam_out = nullptr;
   if (std::is_same<RT, float>::value && s.fast_fwd_ok && !withE) {
-    GatherArgs ga;
-    ga.G = dg; ga.mask = s.maskI[t % 3]; ga.g = nullptr; ga.out = s.Abuf; ga.TI = P.TI;
-    ga.first_piece = s.piece; ga.last_piece = s.piece + dg.n_chunks;
+    const GatherArgs ga = gather_args(s, dg, s.maskI[t % 3], nullptr, P.TI);
     {
       KTime kt(s, st, GABM_KT_GATHER_FWD);
       hipLaunchKernelGGL(k_gather_fast<false>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
     }
     KTime kt(s, st, GABM_KT_AGENT_FWD);
-    hipLaunchKernelGGL(k_agent_fwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a, ga);
+    hipLaunchKernelGGL(k_agent_fwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a, slice_sums(ga));
   } else {
     KTime kt(s, st, GABM_KT_DAY_FWD);
     if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
@@ -487,15 +504,14 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     fm.next = s.gz[(t + 2) % 3];
     fm.clr = s.gz[(t + 1) % 3];
     fm.words = s.mask_words;
-    GatherArgs ga;
-    ga.G = dg; ga.mask = s.gz[t % 3]; ga.g = (const float*)s.g[t & 1]; ga.out = s.Abuf; ga.TI = 1.0;
-    ga.first_piece = s.piece; ga.last_piece = s.piece + dg.n_chunks;
+    const GatherArgs ga = gather_args(s, dg, s.gz[t % 3], (const float*)s.g[t & 1], 1.0);
     if (gather) {
       KTime kt(s, st, GABM_KT_GATHER_BWD);
       hipLaunchKernelGGL(k_gather_fast<true>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
     }
     KTime kt(s, st, GABM_KT_AGENT_BWD);
-    hipLaunchKernelGGL(k_agent_bwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm, ga);
+    hipLaunchKernelGGL(k_agent_bwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm,
+                       slice_sums(ga));
   } else {
     KTime kt(s, st, GABM_KT_DAY_BWD);
     if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);

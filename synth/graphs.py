@@ -75,8 +75,18 @@ def households(n: int, rng: np.random.Generator, lo: int = 1, hi: int = 6):
     consecutive agent ids 0..n-1."""
     sizes = _split_sizes(n, rng, lo, hi)
     starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
-    groups = [np.arange(s0, s0 + s) for s0, s in zip(starts, sizes)]
-    return _clique_pairs(groups)
+    # the pairs _clique_pairs would list for the groups arange(start, start + size)
+    a_parts, b_parts = [], []
+    for s in np.unique(sizes):
+        if s < 2:
+            continue
+        mat = starts[sizes == s][:, None] + np.arange(s)  # [n_groups, s]
+        iu, ju = np.triu_indices(s, 1)
+        a_parts.append(mat[:, iu].reshape(-1))
+        b_parts.append(mat[:, ju].reshape(-1))
+    if not a_parts:
+        return np.zeros(0, np.int64), np.zeros(0, np.int64)
+    return np.concatenate(a_parts), np.concatenate(b_parts)
 
 
 def workplaces(n: int, rng: np.random.Generator, coverage: float = 0.6, lo: int = 5, hi: int = 50):
@@ -90,14 +100,14 @@ def workplaces(n: int, rng: np.random.Generator, coverage: float = 0.6, lo: int 
     return _clique_pairs(groups)
 
 
-def _searchsorted_right(cdf: np.ndarray, r: np.ndarray, bits: int = 22) -> np.ndarray:
+def _searchsorted_right(cdf: np.ndarray, r: np.ndarray) -> np.ndarray:
     """``np.searchsorted(cdf, r, side="right")`` for queries in [0, 1), via a
     table of the answers at the 2^bits grid points: the answer for r in
     [k/L, (k+1)/L) lies between the table entries k and k+1, and the few
     cdf values in between are stepped over one at a time.  The grid points
     and r * L are exact, so the result is identical; random queries into a
     large cdf no longer miss the cache at every bisection step."""
-    L = 1 << bits
+    L = 1 << min(26, max(16, len(cdf).bit_length() + 1))  # about two grid points per cdf value
     tab = np.searchsorted(cdf, np.arange(L + 1, dtype=np.float64) / L, side="right")
     k = (r * L).astype(np.int64)
     pos = tab[k]

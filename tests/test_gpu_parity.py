@@ -258,6 +258,30 @@ def test_persistent_and_tile_kernels_agree(G, O, name, wkw):
     assert_grads(grad_vector(fast), ref["dL"])
 
 
+def test_sender_slices_match_oracle_and_tile_kernels(G, O):
+    """Above 2^20 agents the split kernels read the contact list cut into
+    sender slices of 2^20 agents (one LDS mask each) and add the slices'
+    partial sums per receiver: 1.3M agents give two slices.  Trajectory equal
+    to the oracle's; trajectory and gradients equal to the tile kernels',
+    which read the whole CSR in one pass."""
+    wl = make_workload("c3", n_agents=1_300_000, K=16)
+    _say(f"sender slices c3 N={wl.n_agents} E={wl.n_edges} K={wl.K}")
+    g = graph_of(G, wl)
+    info = g.info()
+    assert info["n_sender_slices"] == 2
+    assert info["n_stream_chunks"] >= (wl.n_edges + 255) // 256
+    tgt = np.linspace(0.0, 2.0, wl.K)
+    fast = run_gpu(G, wl, mode=1, ckpt=5, target=tgt, backward=True, graph=g, schedule=0)
+    tile = run_gpu(G, wl, mode=1, ckpt=5, target=tgt, backward=True, graph=g, schedule=1)
+    assert np.array_equal(fast["counts"], tile["counts"]) and np.array_equal(fast["records"], tile["records"])
+    for k in ("dR", "dS", "dm", "di0"):
+        assert np.allclose(fast[k], tile[k], rtol=1e-6, atol=1e-9 * np.abs(tile[k]).max()), k
+    ref = O.run_workload(wl, mode=O.PLAIN, target=tgt)
+    assert np.array_equal(fast["counts"][0], ref["counts"])
+    assert np.array_equal(fast["drm"][0], ref["drm"])
+    assert fast["loss"][0] == pytest.approx(ref["loss"], rel=1e-12)
+
+
 def test_long_rows_and_edge_cases(G, O):
     _say("long rows / edge cases")
     # a hub with 6000 contacts (longer than one tile) plus a household layer
@@ -299,6 +323,52 @@ def test_full_size_c3_forward_bit_exact(G, O):
     ref = O.run_workload(wl, mode=O.PLAIN, want_stage=False)
     assert np.array_equal(r["counts"][0], ref["counts"])
     assert np.array_equal(r["drm"][0], ref["drm"])
+
+
+def _golden():
+    import importlib.util
+    import os
+
+    fn = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_targets.py")
+    spec = importlib.util.spec_from_file_location("gabm_golden", fn)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.timeout(420)
+def test_full_size_c5(G):
+    """The largest workload (8M agents, about 344M directed contacts per day,
+    120 days, checkpoint every 15 days) in the launch configuration of a
+    benchmark run: float32 state, straight-through gradients, day loops
+    captured in hipGraphs.  The oracle needs minutes for this run, so its
+    result is read from the record tests/golden/make_targets.py --run wrote:
+
+    * daily stage counts and removals equal the oracle's, and so does the
+      FP64 loss;
+    * the mortality gradient equals its closed form (2/K) sum_t (D^t - y^t)
+      drm^t (m reaches the loss only through D = m drm in this mode);
+    * the R and S gradients satisfy sum_t R^t dL/dR^t = sum_a S_a dL/dS_a,
+      since every rate depends on them only through the products R^t S_a."""
+    gold = _golden()
+    ref = gold.read_run("c5")
+    wl = make_workload("c5")
+    _say(f"full c5 N={wl.n_agents} E={wl.n_edges} K={wl.K}")
+    tgt = gold.read_target("c5")[: wl.K]
+    r = run_gpu(G, wl, mode=1, ckpt=15, target=tgt, backward=True, hip_graph=True)
+    assert np.array_equal(r["counts"][0], ref["counts"])
+    assert np.array_equal(r["drm"][0], ref["drm"])
+    assert r["loss"][0] == pytest.approx(ref["loss"], rel=1e-12)
+    m = float(np.float32(wl.m[0]))
+    D = m * ref["drm"]
+    dm = 2.0 / wl.K * np.sum((D - tgt) * ref["drm"])
+    assert r["dm"][0] == pytest.approx(dm, rel=1e-12)
+    R = wl.R[0].astype(np.float64)
+    S = wl.S[0].astype(np.float64)
+    lhs, rhs = np.sum(R * r["dR"][0]), np.sum(S * r["dS"][0])
+    mag = np.sum(np.abs(R * r["dR"][0])) + np.sum(np.abs(S * r["dS"][0]))
+    assert np.all(np.isfinite(r["dR"][0])) and np.all(np.isfinite(r["dS"][0])) and np.isfinite(r["di0"][0])
+    assert abs(lhs - rhs) <= 1e-5 * mag, (lhs, rhs, mag)
 
 
 # ---------------------------------------------------------------- gradients
