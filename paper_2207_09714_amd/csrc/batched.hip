@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(kBBlock) k_bfwd(BFwdArgs a) {
   const BSims& S = a.S;
   for (int x = tid; x < S.B * 6; x += kBBlock) s_cnt[x] = 0u;
   if (ANY_LDS)
-    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.any_cur[x];
+    lds_fill<kBBlock, kBAnyLdsWords>(s_any, a.any_cur, (int)a.any_words);
   // the 'any' words of day t+2 (read last on day t-1, OR-ed next on day t+1)
   for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
     a.any_clr[x] = 0ull;
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(kBBlock, 4) k_bfwd64(BFwdArgs a) {
   const BSims& S = a.S;
   for (int x = tid; x < S.B * 6; x += kBBlock) s_cnt[x] = 0u;
   if (ANY_LDS)
-    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.any_cur[x];
+    lds_fill<kBBlock, kBAnyLdsWords>(s_any, a.any_cur, (int)a.any_words);
   for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
     a.any_clr[x] = 0ull;
   __syncthreads();
@@ -495,7 +495,7 @@ __global__ void __launch_bounds__(kBBlock) k_bbwd(BBwdArgs a) {
   double* s_gi0 = s_gS + (int64_t)S.B * P.n_age;                 // [B]
   for (int x = tid; x < S.B * (P.n_age + 1); x += kBBlock) s_gS[x] = 0.0;
   if (ANY_LDS && a.do_gather)
-    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.gz_cur[x];
+    lds_fill<kBBlock, kBAnyLdsWords>(s_any, a.gz_cur, (int)a.any_words);
   for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
     a.gz_clr[x] = 0ull;
   __syncthreads();
@@ -713,7 +713,7 @@ __global__ void __launch_bounds__(kBBlock, 4) k_bbwd64(BBwdArgs a) {
   double* s_gi0 = s_gS + (int64_t)S.B * P.n_age;                 // [B]
   for (int x = tid; x < S.B * (P.n_age + 1); x += kBBlock) s_gS[x] = 0.0;
   if (ANY_LDS && a.do_gather)
-    for (int64_t x = tid; x < a.any_words; x += kBBlock) s_any[x] = a.gz_cur[x];
+    lds_fill<kBBlock, kBAnyLdsWords>(s_any, a.gz_cur, (int)a.any_words);
   for (int64_t x = blockIdx.x * (int64_t)kBBlock + tid; x < a.any_words; x += (int64_t)gridDim.x * kBBlock)
     a.gz_clr[x] = 0ull;
   __syncthreads();

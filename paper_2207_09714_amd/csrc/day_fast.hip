@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(kFastBlock) k_gather_fast(GatherArgs a) {
     const uint32_t sbase = (uint32_t)p << kSliceShift;
     const int words = (int)min((int64_t)kFastMaskWords, ((int64_t)G.N - sbase + 63) >> 6);
     if (!first) __syncthreads();  // every wave is done with the previous slice's mask
-    for (int x = tid; x < words; x += kFastBlock) mask[x] = a.mask[(sbase >> 6) + x];
+    lds_fill<kFastBlock, kFastMaskWords>(mask, a.mask + (sbase >> 6), words);
     __syncthreads();
     first = false;
     gather_range<BWD>(a, mask, sbase, gbuf, a.out + (int64_t)p * G.N, c0 + (tid >> 6), e, kFastBlock / kWave);

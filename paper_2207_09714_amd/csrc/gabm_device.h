@@ -219,4 +219,32 @@ __device__ __forceinline__ void or_ballot(unsigned long long* mask, int base, un
 
 __device__ __forceinline__ uint32_t mask_bit(const uint32_t* mask32, int c) { return (mask32[c >> 5] >> (c & 31)) & 1u; }
 
+// Copies n <= MAXW 64-bit words from global memory (16-byte aligned) into
+// LDS with a block of NT threads.  Each thread issues all its loads (16 bytes
+// each) before its first LDS write, so the copy costs about one memory round
+// trip rather than one per word a thread moves.
+template <int NT, int MAXW>
+__device__ __forceinline__ void lds_fill(unsigned long long* lds, const unsigned long long* src, int n) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  constexpr int R = (MAXW / 2 + NT - 1) / NT;
+  const int np = n >> 1;  // whole 16-byte pairs
+  const int tid = threadIdx.x;
+  u64x2 v[R];
+  if (np > 0) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = *(const u64x2*)(src + 2 * min(tid + r * NT, np - 1));
+  }
+  const bool tail = (n & 1) && tid == 0;
+  const unsigned long long last = tail ? src[n - 1] : 0ull;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = tid + r * NT;
+    if (x < np) {
+      lds[2 * x] = v[r].x;
+      lds[2 * x + 1] = v[r].y;
+    }
+  }
+  if (tail) lds[n - 1] = last;
+}
+
 }  // namespace gabm
