@@ -41,8 +41,8 @@ KERNEL_SOURCES = ("day_kernels.hip", "day_fast.hip", "agent.h", "tile.h", "gabm_
 
 # kernel class -> device function name as rocprofv3 reports it
 KERNEL_NAMES = {
-    "gather_fwd": "k_gather_fast<false>", "agent_fwd": "k_agent_fwd", "day_fwd": "k_day_fwd",
-    "gather_bwd": "k_gather_fast<true>", "agent_bwd": "k_agent_bwd", "day_bwd": "k_day_bwd", "er": "k_er",
+    "gather_fwd": "k_gather_fast<false>", "agent_fwd": "k_agent_fwd<false>", "day_fwd": "k_day_fwd",
+    "gather_bwd": "k_gather_fast<true>", "agent_bwd": "k_agent_bwd<false>", "day_bwd": "k_day_bwd", "er": "k_er",
 }
 
 
@@ -64,10 +64,16 @@ def load_target(name, K):
     return v[:K] if len(v) >= K else None
 
 
+def traffic_tag(kernel: str) -> str:
+    """File-name tag of a kernel's traffic summary."""
+    return kernel.replace("k_gather_fast<false>", "k_gather_fast_fwd").replace(
+        "k_gather_fast<true>", "k_gather_fast_bwd").split("<")[0]
+
+
 def read_traffic(kernel: str, workload: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when it is missing or was taken on different kernel sources."""
-    tag = kernel.replace("<", "_").replace(">", "").replace("false", "fwd").replace("true", "bwd")
+    tag = traffic_tag(kernel)
     fn = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}.txt")
     if not os.path.exists(fn):
         return None
@@ -127,7 +133,7 @@ def traffic_from_pmc(root: str, workload: str, commands: dict) -> list[str]:
         k = full[0]
         fetch_b = kf[k] * 1024.0 * f_fetch
         write_b = kw[k] * 1024.0 * f_write
-        tag = kname.replace("<", "_").replace(">", "").replace("false", "fwd").replace("true", "bwd")
+        tag = traffic_tag(kname)
         fn = os.path.join(ROOT, "profiles", f"traffic_{tag}_{workload}.txt")
         with open(fn, "w") as fh:
             fh.write(f"# HBM traffic per launch of {kname} on workload {workload} (rocprofv3 --pmc)\n")
@@ -293,7 +299,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4b", "c5"])
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="launches one by one with HIP events around every kernel (default), or the day loops "
                          "captured in hipGraphs (no per-kernel timing)")
@@ -383,12 +389,13 @@ def main():
 
     res = {}
     # kernel schedule picked by the library's autotuner (a few timed forward days per schedule)
-    sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST,
+    pp = dict(n_sets=wl.n_sets, per_pop_params=wl.per_pop_params)
+    sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST, **pp,
                                     ckpt_every=ck, tau_g=wl.tau_g, seed=wl.seed, days=4)
     res["autotune"] = {"schedule": sched, "ms_per_day": sched_ms}
     note(f"autotune: schedule {sched}, ms per day {sched_ms}")
     if args.only in (None, "diff"):
-        sim = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=not eager,
+        sim = gabm.Simulator(g, **pp, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=not eager,
                              time_kernels=TIME_EVERY if eager else 0, tau_g=wl.tau_g, schedule=sched)
         pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
         res["diff_s"] = timed(sim, pb, True, eager)
@@ -400,13 +407,13 @@ def main():
         del sim
         if eager:
             # the same runs with each forward / backward captured in a hipGraph (no per-kernel timing)
-            simg = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=True,
+            simg = gabm.Simulator(g, **pp, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=True,
                                   tau_g=wl.tau_g, schedule=sched)
             pbg = simg.params(wl.R, wl.S, wl.m, wl.i0)
             res["graph_s"] = timed(simg, pbg, True, False)
             del simg
     if args.only in (None, "plain"):
-        simp = gabm.Simulator(g, K=K, Z=wl.Z, mode=gabm.PLAIN, use_hip_graph=not eager,
+        simp = gabm.Simulator(g, **pp, K=K, Z=wl.Z, mode=gabm.PLAIN, use_hip_graph=not eager,
                               time_kernels=TIME_EVERY if eager else 0, schedule=sched)
         pbp = simp.params(wl.R, wl.S, wl.m, wl.i0)
         res["plain_s"] = timed(simp, pbp, False, eager)
@@ -438,7 +445,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{wl.name}: differentiable forward+backward, {N} agents, "
-                        f"{E} directed contacts per day, {K} days, checkpoint every {ck} days, 1 simulation",
+                        f"{E} directed contacts per day, {K} days, "
+                        + (f"checkpoint every {ck} days, " if ck else "every day stored, ")
+                        + (f"{wl.pop.n_pops} packed populations with a parameter set each" if wl.per_pop_params
+                           else "1 simulation"),
             "n_agents": N, "edges_per_day": E, "days": K, "sims_per_step": 1, "ckpt_every": ck,
             "mode": "hard forward, straight-through gradients", "state_storage": "f32",
             "launch": args.launch,

@@ -98,9 +98,12 @@ __device__ __forceinline__ void wstage_gather(const unsigned long long* mask, ui
   }
 }
 
-// DPP move of a lane value with 0 for lanes without a source (or outside the row mask)
+// DPP move of a lane value with 0 for lanes without a source (or outside the
+// row mask).  With every row enabled, bound_ctrl makes a lane without a
+// source read 0, so the destination needs no zeroing first.
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_or0(int v) {
+  if (ROWS == 0xF) return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, true);
   return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, false);
 }
 template <int CTRL, int ROWS>
@@ -155,11 +158,11 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
   seg_scan_step<0x142, 0xA>(ci, xi);  // row_bcast:15 into rows 1 and 3
   seg_scan_step<0x143, 0xC>(ci, xi);  // row_bcast:31 into rows 2 and 3
   int cex = ci - cnt;
-  double sx = __shfl_up(xi, 1);
+  double sx = dpp_or0<0x138, 0xF>(xi);  // wave_shr:1, the previous lane's scan
   int sf = cex > 0;
   if (lane == 0) sx = 0.0;
   // does a row start at the contact after this lane's last one?
-  const uint32_t a_next = __shfl_down(adv[0], 1);
+  const uint32_t a_next = (uint32_t)dpp_or0<0x130, 0xF>((int)adv[0]);  // wave_shl:1
   const uint32_t after = lane == kWave - 1 ? (s.hdr >> 31) : a_next;
   const int64_t rowbase = (int64_t)(s.hdr & 0x7FFFFFFFu);
 #pragma unroll
@@ -273,7 +276,10 @@ __device__ __forceinline__ double gathered(const SliceSums& ga, int i) {
 // ------------------------------------------------------------------ agent passes
 
 // Forward: A = neighbour sum (+ daily random layer), draw, progress, masks of
-// day t+1, counts.
+// day t+1, counts.  Packed populations: each agent uses its population's
+// normaliser and parameter set and counts into its output; a block whose
+// agents share one output reduces its counts first.
+template <bool POPS>
 __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSums ga) {
   __shared__ unsigned scnt[kCnt];
   const int tid = threadIdx.x;
@@ -287,16 +293,23 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
   __syncthreads();
   const int i = blockIdx.x * kBlock + tid;
   const bool on = i < G.N;
+  const int o_blk = POPS ? range_output(G, P, blockIdx.x * kBlock, min(G.N, (blockIdx.x + 1) * kBlock) - 1) : 0;
+  const int slot = blockIdx.x & (kSlots - 1);
+  auto cnt_at = [&](int o) { return a.cnt + (((int64_t)o * P.K + t) * kSlots + slot) * kCnt; };
   uint32_t newst = 0u;
   bool removed = false;
+  int o = 0;
   if (on) {
+    const int p = POPS ? pop_of_agent(G, i) : 0, set = POPS ? set_of(P, p) : 0;
+    const uint32_t loc = (uint32_t)(POPS ? i - G.pop_off[p] : i);
+    o = POPS && P.per_pop ? p : 0;
     double A = gathered(ga, i) * P.TI;
     if (a.A_er) {
       A += a.A_er[i];
       a.A_er[i] = 0.0;
     }
     if (a.A_st) a.A_st[i] = (float)A;
-    const HardDay hd = hard_agent_day(P, a.rng, a.stream, t, 0, 0, (uint32_t)i, G.age[i], A, a.rec_in[i], nullptr);
+    const HardDay hd = hard_agent_day(P, a.rng, a.stream, t, set, p, loc, G.age[i], A, a.rec_in[i], nullptr);
     if (a.fl_st) a.fl_st[i] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
     newst = hd.newst;
     removed = hd.removed;
@@ -306,28 +319,33 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
   const unsigned long long bI = __ballot(on && newst == ST_I);
   if (lane == 0) or_ballot(a.mI_next, blockIdx.x * kBlock + (tid & ~63), bI);
   if (a.cnt) {
-    const unsigned long long c0 = __ballot(on && newst == ST_S), c1 = __ballot(on && newst == ST_E),
-                             c3 = __ballot(on && newst == ST_R), c4 = __ballot(on && newst == ST_M),
-                             c5 = __ballot(on && removed);
-    if (lane == 0) {
-      atomicAdd(&scnt[ST_S], (unsigned)__popcll(c0));
-      atomicAdd(&scnt[ST_E], (unsigned)__popcll(c1));
-      atomicAdd(&scnt[ST_I], (unsigned)__popcll(bI));
-      atomicAdd(&scnt[ST_R], (unsigned)__popcll(c3));
-      atomicAdd(&scnt[ST_M], (unsigned)__popcll(c4));
-      atomicAdd(&scnt[5], (unsigned)__popcll(c5));
-    }
-    __syncthreads();
-    if (tid < 6 && scnt[tid]) {
-      const int slot = blockIdx.x & (kSlots - 1);
-      atomicAdd(&a.cnt[(((int64_t)t) * kSlots + slot) * kCnt + tid], (double)scnt[tid]);
+    if (o_blk >= 0) {
+      const unsigned long long c0 = __ballot(on && newst == ST_S), c1 = __ballot(on && newst == ST_E),
+                               c3 = __ballot(on && newst == ST_R), c4 = __ballot(on && newst == ST_M),
+                               c5 = __ballot(on && removed);
+      if (lane == 0) {
+        atomicAdd(&scnt[ST_S], (unsigned)__popcll(c0));
+        atomicAdd(&scnt[ST_E], (unsigned)__popcll(c1));
+        atomicAdd(&scnt[ST_I], (unsigned)__popcll(bI));
+        atomicAdd(&scnt[ST_R], (unsigned)__popcll(c3));
+        atomicAdd(&scnt[ST_M], (unsigned)__popcll(c4));
+        atomicAdd(&scnt[5], (unsigned)__popcll(c5));
+      }
+      __syncthreads();
+      if (tid < 6 && scnt[tid]) atomicAdd(&cnt_at(o_blk)[tid], (double)scnt[tid]);
+    } else if (on) {  // a block across a population boundary
+      double* c = cnt_at(o);
+      atomicAdd(&c[newst], 1.0);
+      if (removed) atomicAdd(&c[5], 1.0);
     }
   }
 }
 
 // Reverse step t: record inf_bar^t (+ daily random layer) in the window ring,
 // then the adjoint of day t-1 (t >= 1) or of the initial infections (t = 0);
-// g^{t-1} and its non-zero mask for the next step's gather.
+// g^{t-1} and its non-zero mask for the next step's gather.  Parameter-gradient
+// partials are reduced per block when its agents share one parameter set.
+template <bool POPS>
 __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga) {
   __shared__ double sg[2 + 16];
   const int tid = threadIdx.x;
@@ -341,9 +359,15 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
   __syncthreads();
   const int i = blockIdx.x * kBlock + tid;
   const bool on = i < G.N;
+  // the set (= output) of the block when uniform, else -1
+  const int s_blk = POPS ? range_output(G, P, blockIdx.x * kBlock, min(G.N, (blockIdx.x + 1) * kBlock) - 1) : 0;
+  const int slot = blockIdx.x & (kSlots - 1);
   double g_new = 0.0;
-  const double m = P.m[0];
   if (on) {
+    const int p = POPS ? pop_of_agent(G, i) : 0, set = POPS ? set_of(P, p) : 0;
+    const uint32_t loc = (uint32_t)(POPS ? i - G.pop_off[p] : i);
+    const int o = POPS && P.per_pop ? p : 0;
+    const double m = P.m[set];
     double infbar = 0.0;
     if (a.do_gather) {
       infbar = gathered(ga, i);
@@ -362,42 +386,58 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
         const double v = (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
         if (k <= P.tau_E) sE += v; else sI += v;
       }
-      const double drm_bar = (d + W < P.K) ? m * a.Dbar[d + W] : 0.0;
+      const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + W] : 0.0;
       const uint32_t fl = a.fl_st[i];
       const double Aday = (double)a.A_st[i];
-      const AdjOut ad = agent_adjoint<true>(P, a.rng, a.stream, d, 0, 0, (uint32_t)i, age, Aday, (double)(fl & 1u),
-                                      (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
+      const AdjOut ad = agent_adjoint<true>(P, a.rng, a.stream, d, set, p, loc, age, Aday, (double)(fl & 1u),
+                                            (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
       a.Sbar[i] = (float)ad.Sbar;
       a.g_prev[i] = (float)ad.g;
       g_new = (double)(float)ad.g;
       if (ad.lam_bar != 0.0) {
-        const double base = ad.lam_bar * Aday / (double)P.Z[0];
-        atomicAdd(&sg[0], base * (double)P.S[age]);
-        atomicAdd(&sg[2 + age], base * (double)P.R[d]);
+        const double base = ad.lam_bar * Aday / (double)P.Z[p];
+        const double vR = base * (double)P.S[set * P.n_age + age], vS = base * (double)P.R[set * P.K + d];
+        if (s_blk >= 0) {
+          atomicAdd(&sg[0], vR);
+          atomicAdd(&sg[2 + age], vS);
+        } else {
+          atomicAdd(&a.gR[((int64_t)set * P.K + d) * kSlots + slot], vR);
+          atomicAdd(&a.gS[((int64_t)set * P.n_age + age) * kSlots + slot], vS);
+        }
       }
     } else {
       double sI = 0.0;
       for (int k = 0; k < P.tau_I; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
-      const double x0_bar = P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[P.tau_I - 1] : 0.0) - Sbar1;
-      const double u = unit_u(rng_block(a.rng, (uint32_t)i, kDayInit, TAG_INIT, 0u, a.stream).x);
+      const double x0_bar =
+          P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + P.tau_I - 1] : 0.0) - Sbar1;
+      const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, a.stream).x);
       double y0, dy0;
-      relaxed_init((double)P.i0[0], u, P.tau, y0, dy0);
+      relaxed_init((double)P.i0[set], u, P.tau, y0, dy0);
       const double v = x0_bar * dy0;
-      if (v != 0.0) atomicAdd(&sg[1], v);
+      if (v != 0.0) {
+        if (s_blk >= 0) atomicAdd(&sg[1], v);
+        else atomicAdd(&a.gi0[(int64_t)set * kSlots + slot], v);
+      }
     }
   }
   const unsigned long long bz = __ballot(on && g_new != 0.0);
   if ((tid & 63) == 0) or_ballot(fm.next, blockIdx.x * kBlock + (tid & ~63), bz);
   __syncthreads();
-  const int slot = blockIdx.x & (kSlots - 1);
-  if (t >= 1) {
-    if (tid == 0 && sg[0] != 0.0) atomicAdd(&a.gR[((int64_t)(t - 1)) * kSlots + slot], sg[0]);
-    if (tid < P.n_age && sg[2 + tid] != 0.0) atomicAdd(&a.gS[((int64_t)tid) * kSlots + slot], sg[2 + tid]);
-  } else if (tid == 0 && sg[1] != 0.0) {
-    atomicAdd(&a.gi0[slot], sg[1]);
+  if (s_blk >= 0) {
+    if (t >= 1) {
+      if (tid == 0 && sg[0] != 0.0) atomicAdd(&a.gR[((int64_t)s_blk * P.K + (t - 1)) * kSlots + slot], sg[0]);
+      if (tid < P.n_age && sg[2 + tid] != 0.0)
+        atomicAdd(&a.gS[((int64_t)s_blk * P.n_age + tid) * kSlots + slot], sg[2 + tid]);
+    } else if (tid == 0 && sg[1] != 0.0) {
+      atomicAdd(&a.gi0[(int64_t)s_blk * kSlots + slot], sg[1]);
+    }
   }
 }
 
+template __global__ void k_agent_fwd<false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_bwd<false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true>(BwdArgs<float>, FastMasks, SliceSums);
 template __global__ void k_gather_fast<false>(GatherArgs);
 template __global__ void k_gather_fast<true>(GatherArgs);
 

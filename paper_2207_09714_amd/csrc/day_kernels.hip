@@ -37,8 +37,6 @@ __global__ void k_copy_f32(float* d, const float* s, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) d[i] = s[i];
 }
 
-__device__ __forceinline__ int set_of(const DParams& P, int pop) { return P.per_pop ? pop : 0; }
-
 // ----------------------------------------------------------------- initial infections (t = 0)
 // Each agent is infected with probability i0 (Bernoulli on its INIT uniform),
 // entering I with a full timer; the relaxed value y0 is the soft state.

@@ -204,6 +204,15 @@ __device__ __forceinline__ T block_sum(T v, T* scratch) {
 }
 
 __device__ __forceinline__ int pop_of_agent(const DGraph& G, int i) { return G.n_pops == 1 ? 0 : (int)G.pop_of[i]; }
+// parameter set of population p: its own with per-population parameters, else set 0
+__device__ __forceinline__ int set_of(const DParams& P, int pop) { return P.per_pop ? pop : 0; }
+// output (aggregate) index shared by agents [i0, i1], or -1 when they belong to
+// populations with different outputs
+__device__ __forceinline__ int range_output(const DGraph& G, const DParams& P, int i0, int i1) {
+  if (!P.per_pop) return 0;
+  const int p0 = pop_of_agent(G, i0);
+  return p0 == pop_of_agent(G, i1) ? p0 : -1;
+}
 
 // one bit per agent, 64-bit words; OR the ballot of 64 consecutive agents
 // starting at `base` into the mask

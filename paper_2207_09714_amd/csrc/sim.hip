@@ -167,8 +167,8 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
     s.n_cu = ncu;
   }
-  const bool fast_shape = s.schedule == 0 && s.n_cu > 0 && s.B == 1 && !s.per_pop && G.n_pops == 1 &&
-                          G.n_slices > 0 && run->precision == GABM_F32 && s.mode != GABM_SOFT;
+  const bool fast_shape = s.schedule == 0 && s.n_cu > 0 && s.B == 1 && G.n_slices > 0 &&
+                          run->precision == GABM_F32 && s.mode != GABM_SOFT;
   s.fast_fwd_ok = fast_shape;
   s.fast_bwd_ok = fast_shape && s.mode == GABM_HARD_ST;
   s.rsz = run->precision == GABM_F64 ? 8 : 4;
@@ -418,7 +418,12 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
       hipLaunchKernelGGL(k_gather_fast<false>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
     }
     KTime kt(s, st, GABM_KT_AGENT_FWD);
-    hipLaunchKernelGGL(k_agent_fwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a, slice_sums(ga));
+    if (G.n_pops > 1)
+      hipLaunchKernelGGL(k_agent_fwd<true>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a,
+                         slice_sums(ga));
+    else
+      hipLaunchKernelGGL(k_agent_fwd<false>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a,
+                         slice_sums(ga));
   } else {
     KTime kt(s, st, GABM_KT_DAY_FWD);
     if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
@@ -510,8 +515,12 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
       hipLaunchKernelGGL(k_gather_fast<true>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
     }
     KTime kt(s, st, GABM_KT_AGENT_BWD);
-    hipLaunchKernelGGL(k_agent_bwd, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm,
-                       slice_sums(ga));
+    if (G.n_pops > 1)
+      hipLaunchKernelGGL(k_agent_bwd<true>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm,
+                         slice_sums(ga));
+    else
+      hipLaunchKernelGGL(k_agent_bwd<false>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm,
+                         slice_sums(ga));
   } else {
     KTime kt(s, st, GABM_KT_DAY_BWD);
     if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);

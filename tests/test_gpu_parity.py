@@ -241,6 +241,28 @@ def test_forward_trajectory_bit_exact(G, O, name, wkw, rkw):
     assert np.array_equal(st, ref["stage"][-1])
 
 
+def test_packed_populations_gradients(G, O):
+    """Packed populations, each with its own parameter set, on the split
+    kernels (blocks of agents that straddle two populations count and reduce
+    per agent): each population's trajectory and gradients equal the oracle's
+    run of that population alone, and the tile kernels agree."""
+    wl = make_workload("c4b", n_agents=5000, K=16, n_pops=4)
+    _say(f"packed populations N={wl.n_agents} pops={wl.pop.n_pops} offsets={list(wl.pop.pop_offsets)}")
+    assert any(int(o) % 256 for o in wl.pop.pop_offsets[1:-1])
+    tgt = np.linspace(0.0, 0.5, wl.K)
+    fast = run_gpu(G, wl, mode=1, ckpt=5, target=tgt, backward=True, schedule=0)
+    tile = run_gpu(G, wl, mode=1, ckpt=5, target=tgt, backward=True, schedule=1)
+    assert np.array_equal(fast["counts"], tile["counts"]) and np.array_equal(fast["records"], tile["records"])
+    for k in ("dR", "dS", "dm", "di0"):
+        assert np.allclose(fast[k], tile[k], rtol=1e-6, atol=1e-9 * np.abs(tile[k]).max()), k
+    dirs = O.standard_directions(wl.K, 8)
+    for p in range(wl.pop.n_pops):
+        ref = O.run_workload(wl, pop_index=p, mode=O.HARD_ST, target=tgt, directions=dirs)
+        assert np.array_equal(fast["counts"][p], ref["counts"]), p
+        got = np.concatenate([[fast["dR"][p].sum()], fast["dS"][p], [fast["dm"][p]], [fast["di0"][p]]])
+        assert_grads(got, ref["dL"])
+
+
 @pytest.mark.parametrize("name,wkw", [("c3", dict(n_agents=40000, K=30)), ("c2", dict(n_agents=6000, K=20))])
 def test_persistent_and_tile_kernels_agree(G, O, name, wkw):
     """The persistent LDS-mask kernels and the receiver-tile kernels give the
