@@ -303,6 +303,8 @@ def main():
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="launches one by one with HIP events around every kernel (default), or the day loops "
                          "captured in hipGraphs (no per-kernel timing)")
+    ap.add_argument("--schedule", type=int, default=None,
+                    help="kernel schedule of the single-workload legs (default: the autotuner's choice)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-days", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (c4a) legs")
@@ -316,8 +318,8 @@ def main():
     if args.traffic_from:
         pmc = "timeout -s KILL 120 rocprofv3 --pmc {c} --output-format csv -d {d} -o run -- python3 bench.py {a}"
         cmds = {
-            "fetch": pmc.format(c="FETCH_SIZE", d=f"{args.traffic_from}/fetch", a="--only diff --steps 1 --warmup 0 --no-cpu-baseline"),
-            "write": pmc.format(c="WRITE_SIZE", d=f"{args.traffic_from}/write", a="--only diff --steps 1 --warmup 0 --no-cpu-baseline"),
+            "fetch": pmc.format(c="FETCH_SIZE", d=f"{args.traffic_from}/fetch", a="--only diff --steps 1 --warmup 0 --no-cpu-baseline --schedule 0"),
+            "write": pmc.format(c="WRITE_SIZE", d=f"{args.traffic_from}/write", a="--only diff --steps 1 --warmup 0 --no-cpu-baseline --schedule 0"),
             "copy fetch": pmc.format(c="FETCH_SIZE", d=f"{args.traffic_from}/copy_fetch", a="--only copy"),
             "copy write": pmc.format(c="WRITE_SIZE", d=f"{args.traffic_from}/copy_write", a="--only copy"),
             "summary": f"python bench.py --traffic-from {args.traffic_from} --workload {args.workload}",
@@ -393,6 +395,9 @@ def main():
     sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST, **pp,
                                     ckpt_every=ck, tau_g=wl.tau_g, seed=wl.seed, days=4)
     res["autotune"] = {"schedule": sched, "ms_per_day": sched_ms}
+    if args.schedule is not None:
+        sched = args.schedule
+        res["autotune"]["overridden_by"] = sched
     note(f"autotune: schedule {sched}, ms per day {sched_ms}")
     if args.only in (None, "diff"):
         sim = gabm.Simulator(g, **pp, K=K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=ck, use_hip_graph=not eager,

@@ -26,8 +26,12 @@
 
 namespace gabm {
 
-__device__ __forceinline__ uint32_t lds_bit(const unsigned long long* m, int c) {
-  return (uint32_t)(m[c >> 6] >> (c & 63)) & 1u;
+// mask bit of a sender of the slice held in LDS: the slice's senders lie in
+// [p << kSliceShift, (p + 1) << kSliceShift), so the low kSliceShift bits are
+// the slice-local index; 32-bit words, one bit-field extract
+__device__ __forceinline__ uint32_t lds_bit(const unsigned long long* m, uint32_t sender) {
+  const uint32_t c = sender & ((1u << kSliceShift) - 1u);
+  return __builtin_amdgcn_ubfe(((const uint32_t*)m)[c >> 5], c & 31u, 1u);
 }
 
 // ---------------------------------------------------------------- wave-parallel neighbour sum
@@ -87,13 +91,15 @@ __device__ __forceinline__ void wstage_load(const GatherArgs& a, WStage& s, int6
 // branch around the load (a branch would make the compiler wait for it at
 // once).
 template <bool BWD>
-__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, uint32_t sbase,
-                                              __amdgpu_buffer_rsrc_t gbuf, WStage& s) {
+__device__ __forceinline__ void wstage_gather(const unsigned long long* mask, __amdgpu_buffer_rsrc_t gbuf,
+                                              WStage& s) {
   if (!BWD) return;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint32_t c = s.p[j] & 0xFFFFFFu;
-    const uint32_t off = lds_bit(mask, (int)(c - sbase)) ? c * 4u : 0x80000000u;
+    // one common out-of-range offset for clear bits: the address unit then
+    // sees a single line for all of them
+    const uint32_t off = lds_bit(mask, c) ? c * 4u : 0x80000000u;
     s.g[j] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(gbuf, off, 0, 0));
   }
 }
@@ -124,16 +130,20 @@ __device__ __forceinline__ void seg_scan_step(int& c, double& x) {
 }
 
 template <bool BWD>
-__device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned long long* mask, uint32_t sbase,
-                                           double* out, const WStage& s, int64_t k) {
+__device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned long long* mask, double* out,
+                                           const WStage& s, int64_t k) {
   const int lane = threadIdx.x & 63;
   uint32_t adv[4];
   double v[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     adv[j] = s.p[j] >> 24;
-    const int c = (int)((s.p[j] & 0xFFFFFFu) - sbase);
-    v[j] = BWD ? (double)s.w[j] * (double)s.g[j] : (lds_bit(mask, c) ? (double)s.w[j] : 0.0);
+    if (BWD) {
+      v[j] = (double)s.w[j] * (double)s.g[j];
+    } else {  // the weight where the sender's bit is set, else +0
+      const uint32_t keep = 0u - lds_bit(mask, s.p[j] & 0xFFFFFFu);
+      v[j] = (double)__uint_as_float(__float_as_uint(s.w[j]) & keep);
+    }
   }
   // this lane's open segment and row-start count
   int cnt = 0;
@@ -195,7 +205,7 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
 // chunk c is reduced in step c, its contacts were requested kStages - 1 steps
 // earlier and (reverse) its adjoints kGatherAhead steps earlier.
 template <bool BWD>
-__device__ __forceinline__ void gather_range(const GatherArgs& a, const unsigned long long* mask, uint32_t sbase,
+__device__ __forceinline__ void gather_range(const GatherArgs& a, const unsigned long long* mask,
                                              __amdgpu_buffer_rsrc_t gbuf, double* out, int64_t start, int64_t end,
                                              int stride) {
   if (start >= end) return;
@@ -205,14 +215,14 @@ __device__ __forceinline__ void gather_range(const GatherArgs& a, const unsigned
 #pragma unroll
   for (int j = 0; j < kStages - 1; ++j) wstage_load(a, st[j], chunk(j));
 #pragma unroll
-  for (int j = 0; j < kGatherAhead; ++j) wstage_gather<BWD>(mask, sbase, gbuf, st[j]);
+  for (int j = 0; j < kGatherAhead; ++j) wstage_gather<BWD>(mask, gbuf, st[j]);
   for (int64_t q = 0; q < mine; q += kStages) {
 #pragma unroll
     for (int j = 0; j < kStages; ++j) {
       if (q + j >= mine) break;
       wstage_load(a, st[(j + kStages - 1) % kStages], chunk(q + j + kStages - 1));
-      wstage_gather<BWD>(mask, sbase, gbuf, st[(j + kGatherAhead) % kStages]);
-      wave_chunk<BWD>(a, mask, sbase, out, st[j], chunk(q + j));
+      wstage_gather<BWD>(mask, gbuf, st[(j + kGatherAhead) % kStages]);
+      wave_chunk<BWD>(a, mask, out, st[j], chunk(q + j));
     }
   }
 }
@@ -244,7 +254,7 @@ __global__ void __launch_bounds__(kFastBlock) k_gather_fast(GatherArgs a) {
     lds_fill<kFastBlock, kFastMaskWords>(mask, a.mask + (sbase >> 6), words);
     __syncthreads();
     first = false;
-    gather_range<BWD>(a, mask, sbase, gbuf, a.out + (int64_t)p * G.N, c0 + (tid >> 6), e, kFastBlock / kWave);
+    gather_range<BWD>(a, mask, gbuf, a.out + (int64_t)p * G.N, c0 + (tid >> 6), e, kFastBlock / kWave);
     c0 = e;
     ++p;
   }
