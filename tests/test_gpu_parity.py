@@ -304,6 +304,64 @@ def test_sender_slices_match_oracle_and_tile_kernels(G, O):
     assert fast["loss"][0] == pytest.approx(ref["loss"], rel=1e-12)
 
 
+def test_packed_populations_across_sender_slices(G, O):
+    """1.6M agents in 4 packed populations: two sender slices, one population
+    across the slice border, and runs of hundreds of thousands of rows that are
+    empty within a slice (kept below 256 per row-start byte by zero-weight
+    contacts).  Each population's trajectory equals the oracle's; the split
+    and tile kernels agree on trajectories and gradients."""
+    wl = make_workload("c4b", n_agents=800_000, K=8, n_pops=4)
+    offs = [int(o) for o in wl.pop.pop_offsets]
+    _say(f"packed populations across slices N={wl.n_agents} offsets={offs}")
+    assert any(a < (1 << 20) < b for a, b in zip(offs[:-1], offs[1:]))
+    g = graph_of(G, wl)
+    assert g.info()["n_sender_slices"] == 2
+    tgt = np.linspace(0.0, 1.0, wl.K)
+    fast = run_gpu(G, wl, mode=1, ckpt=3, target=tgt, backward=True, graph=g, schedule=0)
+    tile = run_gpu(G, wl, mode=1, ckpt=3, target=tgt, backward=True, graph=g, schedule=1)
+    assert np.array_equal(fast["counts"], tile["counts"]) and np.array_equal(fast["records"], tile["records"])
+    for k in ("dR", "dS", "dm", "di0"):
+        assert np.allclose(fast[k], tile[k], rtol=1e-6, atol=1e-9 * np.abs(tile[k]).max()), k
+    for p in range(wl.pop.n_pops):
+        ref = O.run_workload(wl, pop_index=p, mode=O.PLAIN, target=tgt)
+        assert np.array_equal(fast["counts"][p], ref["counts"]), p
+        assert fast["loss"][p] == pytest.approx(ref["loss"], rel=1e-12), p
+
+
+@pytest.mark.parametrize("n", [(1 << 20), (1 << 20) + 1])
+def test_sender_slice_boundaries(G, O, n):
+    """Households only (sparse rows, many of them empty within a slice) on
+    exactly 2^20 agents (one slice) and 2^20 + 1 (a second slice holding one
+    agent's contacts): trajectories equal the oracle's, gradients equal the
+    tile kernels'."""
+    from synth.graphs import households, quantized_unit_weights, to_symmetric_coo
+
+    rng = np.random.default_rng(n)
+    ha, hb = households(n, rng)
+    src, dst, w = to_symmetric_coo([(ha, hb, quantized_unit_weights(rng, len(ha)))])
+    age = (np.arange(n) % 8).astype(np.uint8)
+    K = 8
+    Z = np.float32(5.0 * float(np.sum(w, dtype=np.float64)) / n)
+    S = np.linspace(0.5, 1, 8).astype(np.float32)
+    g = G.Graph(n_agents=n, src=src, dst=dst, w=w, age=age)
+    assert g.info()["n_sender_slices"] == (1 if n == (1 << 20) else 2)
+    tgt = torch.tensor(np.linspace(0.0, 50.0, K), device="cuda")
+    res = {}
+    for sched in (0, 1):
+        sim = G.Simulator(g, K=K, Z=[Z], mode=G.HARD_ST, ckpt_every=3, schedule=sched)
+        pb = sim.params(np.full(K, 4.0, np.float32), S, [0.05], [0.05])
+        out = sim.forward(pb, seed=5, target=tgt)
+        r = {k: v.cpu().numpy().copy() for k, v in out.items()}
+        r.update({k: v.cpu().numpy().copy() for k, v in sim.backward(pb, seed=5).items()})
+        res[sched] = r
+    ref = O.run(age=age, pop_offsets=[0, n], src=src, dst=dst, w=w, K=K, R=4.0, S=S, m=0.05, i0=0.05, Z=Z,
+                mode=O.PLAIN, seed=5, target=tgt.cpu().numpy())
+    assert np.array_equal(res[0]["counts"][0], ref["counts"])
+    assert np.array_equal(res[1]["counts"][0], ref["counts"])
+    for k in ("dR", "dS", "dm", "di0"):
+        assert np.allclose(res[0][k], res[1][k], rtol=1e-6, atol=1e-9 * np.abs(res[1][k]).max()), k
+
+
 def test_long_rows_and_edge_cases(G, O):
     _say("long rows / edge cases")
     # a hub with 6000 contacts (longer than one tile) plus a household layer
