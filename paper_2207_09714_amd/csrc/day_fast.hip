@@ -58,6 +58,10 @@ constexpr long long kPiecedTag = 0x7FFDA00000000000LL;
 constexpr long long kPiecedMask = (long long)0xFFFFF00000000000ULL;
 static_assert(kPieceChunkBits + kPieceBackBits == 44, "piece marker payload");
 constexpr int kXcds = 8;  // workgroups are dispatched round-robin over the XCDs
+// row-end stores of the forward / reverse gathers: compacted per lane, and the
+// two pieces of a chunk in one 16-byte store
+constexpr bool kCompactFwd = false, kCompactBwd = true;
+constexpr bool kPairFwd = false, kPairBwd = true;
 // software pipeline of the persistent gather (kGatherAhead <= kStages - 2)
 constexpr int kStages = 3;
 constexpr int kGatherAhead = 1;
@@ -175,6 +179,18 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
   const uint32_t a_next = (uint32_t)dpp_or0<0x130, 0xF>((int)adv[0]);  // wave_shl:1
   const uint32_t after = lane == kWave - 1 ? (s.hdr >> 31) : a_next;
   const int64_t rowbase = (int64_t)(s.hdr & 0x7FFFFFFFu);
+  // Row ends.  A row that began in an earlier chunk gets the piece marker
+  // and its sum goes to the chunk's first piece.
+  constexpr bool COMPACT = BWD ? kCompactBwd : kCompactFwd;
+  constexpr bool PAIR = BWD ? kPairBwd : kPairFwd;
+  const double marker = __longlong_as_double(kPiecedTag | ((long long)s.back << kPieceChunkBits) | k);
+  bool has_first = false;
+  double first = 0.0;
+  // COMPACT: the rows ending in this lane's contacts go to slots 0..3 first,
+  // so the wave issues one store per slot some lane uses (usually one)
+  double val[4];
+  uint32_t rw[4];
+  int n_end = 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     if (adv[j]) {
@@ -185,18 +201,56 @@ __device__ __forceinline__ void wave_chunk(const GatherArgs& a, const unsigned l
     cex += (int)adv[j];
     const uint32_t anext = j < 3 ? adv[j + 1] : after;
     if (anext) {  // the row of contact j ends here
-      const int64_t row = rowbase + cex - 1;
-      if (sf) {
-        out[row] = sx;
-      } else {  // the row began in an earlier chunk: its sum is assembled from pieces
-        a.first_piece[k] = sx;
-        out[row] = __longlong_as_double(kPiecedTag | ((long long)s.back << kPieceChunkBits) | k);
+      if (!sf) {
+        has_first = true;
+        first = sx;
+      }
+      const double x = sf ? sx : marker;
+      const uint32_t r = (uint32_t)(rowbase + cex - 1);
+      if (COMPACT) {
+#pragma unroll
+        for (int q = 0; q <= j; ++q)
+          if (n_end == q) {
+            val[q] = x;
+            rw[q] = r;
+          }
+        ++n_end;
+      } else {
+        if (!sf && !PAIR) a.piece[2 * k] = sx;
+        out[r] = x;
       }
     }
   }
-  if (lane == kWave - 1 && after == 0) {  // the chunk's last row continues
-    if (sf) a.last_piece[k] = sx;
-    else a.first_piece[k] = sx;
+  if (COMPACT) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (n_end > q) out[rw[q]] = val[q];
+    if (!PAIR && has_first) a.piece[2 * k] = first;
+  }
+  if (PAIR) {
+    // one 16-byte store from the last lane: the first piece (the continuing
+    // row's part, or the whole chunk when no row starts in it) and the last
+    // piece (the part of the chunk's last row that continues)
+    const unsigned long long fm = __ballot(has_first);  // at most one lane
+    double fp_row = 0.0;
+    if (fm) {  // wave-uniform
+      const int src = __builtin_ctzll(fm);
+      const long long b = __double_as_longlong(first);
+      const int lo = __builtin_amdgcn_readlane((int)b, src), hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+      fp_row = __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+    }
+    if (lane == kWave - 1) {
+      double fp = fp_row, lp = 0.0;
+      if (after == 0) {  // the chunk's last row continues
+        if (sf) lp = sx;
+        else fp = sx;
+      }
+      typedef double f64x2 __attribute__((ext_vector_type(2)));
+      *(f64x2*)(a.piece + 2 * k) = f64x2{fp, lp};
+    }
+  } else if (lane == kWave - 1 && after == 0) {  // the chunk's last row continues
+    if (sf) a.piece[2 * k + 1] = sx;
+    else a.piece[2 * k] = sx;
   }
 }
 
@@ -271,8 +325,8 @@ __device__ __forceinline__ double gathered_slice(const SliceSums& ga, int p, int
   if ((bits & kPiecedMask) != kPiecedTag) return v;
   const int64_t kB = bits & ((1LL << kPieceChunkBits) - 1);
   const int64_t kA = kB - ((bits >> kPieceChunkBits) & ((1LL << kPieceBackBits) - 1));
-  double s = ga.last_piece[kA];
-  for (int64_t k = kA + 1; k <= kB; ++k) s += ga.first_piece[k];
+  double s = ga.piece[2 * kA + 1];
+  for (int64_t k = kA + 1; k <= kB; ++k) s += ga.piece[2 * k];
   return s;
 }
 

@@ -139,16 +139,14 @@ struct GatherArgs {
   const unsigned long long* mask;  // one bit per agent
   const float* g;                  // reverse: rate adjoints (read where the bit is set)
   double* out;                     // [n_slices][N] per-slice row sums (or a piece marker)
-  double* first_piece;             // [chunks]
-  double* last_piece;              // [chunks]
+  double* piece;                   // [chunks][2]: first piece, last piece
   double TI;
 };
 
 // the neighbour sums as the agent pass reads them
 struct SliceSums {
   const double* out;          // [n_slices][N]
-  const double* first_piece;  // [chunks]
-  const double* last_piece;   // [chunks]
+  const double* piece;        // [chunks][2]: first piece, last piece
   int64_t N;
   int32_t n_slices;
 };
@@ -156,8 +154,7 @@ struct SliceSums {
 inline SliceSums slice_sums(const GatherArgs& a) {
   SliceSums s;
   s.out = a.out;
-  s.first_piece = a.first_piece;
-  s.last_piece = a.last_piece;
+  s.piece = a.piece;
   s.N = a.G.N;
   s.n_slices = a.n_slices;
   return s;

@@ -344,8 +344,7 @@ static GatherArgs gather_args(const Sim& s, const DGraph& dg, const unsigned lon
   ga.mask = mask;
   ga.g = g;
   ga.out = s.Abuf;
-  ga.first_piece = s.piece;
-  ga.last_piece = s.piece + G.slice_chunk.back();
+  ga.piece = s.piece;
   ga.TI = TI;
   return ga;
 }
