@@ -79,24 +79,33 @@ __device__ __forceinline__ AdjOut agent_adjoint(const DParams& P, Rng rng, uint3
                                                 uint32_t loc, int age, double A, double Sv, double h, bool soft,
                                                 double sE, double sI, double Sbar1, double drm_bar) {
   const double xi_bar = drm_bar + P.TI * sI + P.TE * sE - Sbar1;
-  const double Rt = P.R[set * P.K + d], Sa = P.S[set * P.n_age + age], Zp = P.Z[p];
+  const float* Rp = P.R + set * P.K + d;
+  const float* Sp = P.S + set * P.n_age + age;
   double dydl = 0.0;
+  AdjOut o;
+  if (LOWP) {  // rate, derivative and g in single precision (gradients only)
+    const float rs_z = *Rp * *Sp / P.Z[p];
+    if (soft || (Sv != 0.0 && A > 0.0)) {
+      const double u = unit_u(rng_block(rng, loc, (uint32_t)d, TAG_INFECT, (uint32_t)p, stream).x);
+      float yf, df;
+      relaxed_sample_f(rs_z * (float)A, (float)u, (float)P.tau, yf, df);
+      dydl = (double)df;
+      if (soft) h = (double)yf;
+    }
+    o.Sbar = Sbar1 + h * xi_bar;
+    o.lam_bar = Sv * xi_bar * dydl;
+    o.g = (double)(rs_z * (float)o.lam_bar);
+    return o;
+  }
+  const double Rt = *Rp, Sa = *Sp, Zp = P.Z[p];
   if (soft || (Sv != 0.0 && A > 0.0)) {
     const double lam = rate(Rt, Sa, A, Zp);
     const double u = unit_u(rng_block(rng, loc, (uint32_t)d, TAG_INFECT, (uint32_t)p, stream).x);
-    if (LOWP) {
-      float yf, df;
-      relaxed_sample_f((float)lam, (float)u, (float)P.tau, yf, df);
-      dydl = (double)df;
-      if (soft) h = (double)yf;
-    } else {
-      const double q = -expm1(-lam);
-      double y;
-      relaxed_sample(lam, q, u, P.tau, y, dydl);
-      if (soft) h = y;
-    }
+    const double q = -expm1(-lam);
+    double y;
+    relaxed_sample(lam, q, u, P.tau, y, dydl);
+    if (soft) h = y;
   }
-  AdjOut o;
   o.Sbar = Sbar1 + h * xi_bar;
   o.lam_bar = Sv * xi_bar * dydl;
   o.g = Rt * Sa / Zp * o.lam_bar;

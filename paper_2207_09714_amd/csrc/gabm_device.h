@@ -91,23 +91,26 @@ __device__ __forceinline__ void relaxed_sample(double lam, double q, double u, d
 
 // The same in single precision, for runs that store float state: the
 // derivative feeds only the reverse pass (gradients), never a hard decision.
-__device__ __forceinline__ float sigm_f(float z) {
-  if (z >= 0.f) return 1.f / (1.f + expf(-z));
-  const float e = expf(z);
-  return e / (1.f + e);
-}
-__device__ __forceinline__ float log_sigm_f(float z) { return z >= 0.f ? -log1pf(expf(-z)) : z - log1pf(expf(z)); }
+// With l = log((1-u)/u) (1-u is exact for these u), z tau = log(q) + lambda + l
+// = log(expm1(lambda)) + l, so log q = z tau - lambda - l needs no logarithm of
+// its own, and sigma(z), sigma(-z), log sigma(z) share e = exp(-|z|).
 __device__ __forceinline__ void relaxed_sample_f(float lam, float u, float tau, float& y, float& dydl) {
-  const float q = -expm1f(-lam);
-  if (!(q > 0.f)) {
+  if (!(lam > 0.f)) {
     y = 0.f;
     dydl = 0.f;
     return;
   }
-  const float lq = logf(q);
-  const float z = (lq + lam + (log1pf(-u) - logf(u))) / tau;
-  y = sigm_f(z);
-  dydl = expf(log_sigm_f(z) - lq) * sigm_f(-z) / tau;
+  const float it = 1.f / tau;
+  const float l = logf((1.f - u) / u);
+  const float zt = (lam < 20.f ? logf(expm1f(lam)) : lam) + l;  // log(e^lambda - 1) = lambda to float precision above 20
+  const float z = zt * it;
+  const float e = expf(-fabsf(z));
+  const float r = 1.f / (1.f + e);
+  const bool pos = z >= 0.f;
+  y = pos ? r : e * r;
+  const float s_neg = pos ? e * r : r;                  // sigma(-z)
+  const float log_s = (pos ? 0.f : z) - log1pf(e);       // log sigma(z)
+  dydl = expf(log_s - (zt - lam - l)) * s_neg * it;     // sigma(z) sigma(-z) / (tau q)
 }
 
 // y0 and dy0/di0 of the relaxed initial infection

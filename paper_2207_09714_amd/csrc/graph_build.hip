@@ -173,7 +173,7 @@ __global__ void k_sort_short(const int64_t* row_ptr, int32_t N, int32_t* col, fl
   }
 }
 
-constexpr int kSortLds = 4096;
+constexpr int kSortLds = 8192;
 
 // rows longer than 32: one block per row, bitonic sort of the packed keys in
 // LDS (rows up to kSortLds) or in a global scratch area (longer rows)
