@@ -225,8 +225,10 @@ typedef struct {
   int32_t precision;   /* GABM_F32 or GABM_F64 storage */
   int32_t use_hip_graph; /* capture each forward segment / backward day loop in a hipGraph */
   int32_t schedule;    /* 0: choose per simulation (B = 1: persistent LDS-mask kernels when
-                          eligible: float state, one parameter set and population, up to 2^20
-                          agents; B > 32: one wave per tile with 64-contact windows);
+                          eligible: float state, hard or straight-through mode, T_E = 0, fewer
+                          than 2^24 agents (one LDS mask per slice of 2^20 senders), one
+                          parameter set or one per packed population; B > 32: one wave per
+                          tile with 64-contact windows);
                           1: receiver-tile kernels (B = 1) / lane-group kernels (B > 1) only.
                           gabm_autotune picks between them by measurement. */
   int32_t time_kernels; /* k > 0: record HIP events around every k-th launch of each class of day
