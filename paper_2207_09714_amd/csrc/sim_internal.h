@@ -64,8 +64,8 @@ struct Sim {
   size_t ev_used = 0;
   hipEvent_t next_event();
 
-  // persistent kernels (float state, one parameter set, one population, up to
-  // 2^20 agents): eligibility and the non-zero masks of the rate adjoint
+  // persistent kernels (float state, one simulation, fewer than 2^24 agents):
+  // eligibility and the non-zero masks of the rate adjoint
   int n_cu = 0;
   int schedule = 0;  // 0 auto, 1 tile kernels only
   bool fast_fwd_ok = false, fast_bwd_ok = false;
