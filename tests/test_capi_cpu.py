@@ -99,3 +99,37 @@ def test_python_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_lib, "_lib", None)
     with pytest.raises(ImportError):
         _lib.lib()
+
+
+def test_binding_structs_match_the_header(L, tmp_path):
+    """Every struct the binding passes across the ABI has the size and field
+    offsets the C header gives it (the header compiled by the host C compiler)."""
+    import shutil
+    import subprocess
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"gabm_graph_desc": L.GraphDesc, "gabm_graph_stats": L.GraphStats, "gabm_params": L.Params,
+               "gabm_rng": L.Rng, "gabm_run_desc": L.RunDesc, "gabm_kernel_times": L.KernelTimes,
+               "gabm_fwd_out": L.FwdOut, "gabm_grads": L.Grads}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "gabm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            cname, key, val = line.split()
+            got[(cname, key)] = int(val)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
