@@ -249,3 +249,40 @@ def test_autotune_picks_a_schedule_that_matches(G, n_sets, n_reps, name):
         pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
         res.append(sim.forward(pb, seed=wl.seed)["counts"].cpu().numpy().copy())
     assert np.array_equal(res[0], res[1])
+
+
+@pytest.mark.timeout(420)
+def test_full_size_c4a_sampled(G, O):
+    """The full batched workload (250k agents, 9.5M contacts per day, 45 days,
+    64 parameter sets x 2 replicates) in the benchmark's launch configuration
+    (the autotuner's schedule, every day kept, an all-zero deaths target).
+    Four simulations -- both replicates, both ends of the lane layout -- equal
+    their own oracle runs bit for bit (daily counts, removals, final stages).
+    Per set, dL/dm equals its closed form (2/K) sum_reps sum_t (D - y) drm, and
+    sum_t R^t dL/dR^t = sum_a S_a dL/dS_a (rates depend on R and S only
+    through their products)."""
+    wl = make_workload("c4a")
+    B = wl.n_sets * wl.n_reps
+    _say(f"full c4a N={wl.n_agents} E={wl.n_edges} K={wl.K} B={B}")
+    g = graph_of(G, wl)
+    sched, _ = G.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=wl.K, n_sets=wl.n_sets, n_reps=wl.n_reps,
+                          mode=G.HARD_ST, ckpt_every=wl.ckpt_every, tau_g=wl.tau_g, seed=wl.seed, days=4)
+    sim = G.Simulator(g, n_sets=wl.n_sets, n_reps=wl.n_reps, K=wl.K, Z=wl.Z, mode=G.HARD_ST,
+                      ckpt_every=wl.ckpt_every, tau_g=wl.tau_g, schedule=sched)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    tgt = np.zeros(wl.K)
+    out = sim.forward(pb, seed=wl.seed, target=torch.tensor(tgt, device="cuda"))
+    r = {k: v.cpu().numpy().copy() for k, v in out.items()}
+    r.update({k: v.cpu().numpy().copy() for k, v in sim.backward(pb, seed=wl.seed).items()})
+    r["records"] = sim.records().cpu().numpy().reshape(wl.n_agents, -1)
+    check_forward(O, wl, r, mode=O.PLAIN, sims=[0, wl.n_sets - 1, wl.n_sets, B - 1])
+    for s in range(wl.n_sets):
+        m = float(np.float32(wl.m[s]))
+        dm = sum(2.0 / wl.K * np.sum((m * r["drm"][s + q * wl.n_sets] - tgt) * r["drm"][s + q * wl.n_sets])
+                 for q in range(wl.n_reps))
+        assert r["dm"][s] == pytest.approx(dm, rel=1e-12), s
+        R = wl.R[s].astype(np.float64)
+        S = wl.S[s].astype(np.float64)
+        lhs, rhs = np.sum(R * r["dR"][s]), np.sum(S * r["dS"][s])
+        mag = np.sum(np.abs(R * r["dR"][s])) + np.sum(np.abs(S * r["dS"][s]))
+        assert abs(lhs - rhs) <= 1e-5 * mag, (s, lhs, rhs, mag)

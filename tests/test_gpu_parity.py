@@ -451,6 +451,53 @@ def test_full_size_c5(G):
     assert abs(lhs - rhs) <= 1e-5 * mag, (lhs, rhs, mag)
 
 
+@pytest.mark.timeout(420)
+def test_full_size_c4b_sampled(G, O):
+    """The full packed workload (24 populations, 2.48M agents, 94M contacts
+    per day, 45 days, a parameter set per population, every day kept) in the
+    benchmark's launch configuration.  The smallest, a middle and the largest
+    population equal the oracle's run of that population alone (daily counts,
+    removals, loss); every population's dL/dm equals its closed form and its
+    R and S gradients satisfy the homogeneity identity."""
+    wl = make_workload("c4b")
+    sizes = np.diff(wl.pop.pop_offsets)
+    _say(f"full c4b N={wl.n_agents} E={wl.n_edges} K={wl.K} pops={wl.pop.n_pops}")
+    tgt = np.linspace(0.0, 20.0, wl.K)
+    r = run_gpu(G, wl, mode=1, ckpt=wl.ckpt_every, target=tgt, backward=True)
+    order = np.argsort(sizes)
+    for p in (int(order[0]), int(order[len(order) // 2]), int(order[-1])):
+        ref = O.run_workload(wl, pop_index=p, mode=O.PLAIN, target=tgt)
+        assert np.array_equal(r["counts"][p], ref["counts"]), p
+        assert np.array_equal(r["drm"][p], ref["drm"]), p
+        assert r["loss"][p] == pytest.approx(ref["loss"], rel=1e-12), p
+    for p in range(wl.pop.n_pops):
+        m = float(np.float32(wl.m[p]))
+        dm = 2.0 / wl.K * np.sum((m * r["drm"][p] - tgt) * r["drm"][p])
+        assert r["dm"][p] == pytest.approx(dm, rel=1e-12), p
+        R = wl.R[p].astype(np.float64)
+        S = wl.S[p].astype(np.float64)
+        lhs, rhs = np.sum(R * r["dR"][p]), np.sum(S * r["dS"][p])
+        mag = np.sum(np.abs(R * r["dR"][p])) + np.sum(np.abs(S * r["dS"][p]))
+        assert abs(lhs - rhs) <= 1e-5 * mag, (p, lhs, rhs, mag)
+
+
+@pytest.mark.timeout(300)
+def test_full_size_c2(G, O):
+    """The full 100k-agent workload with its daily random layer (60 days,
+    checkpoint every 10 days, the stored target): trajectory equal to the
+    oracle's, gradients equal to the oracle's forward-mode tangents."""
+    gold = _golden()
+    wl = make_workload("c2")
+    tgt = gold.read_target("c2")[: wl.K]
+    _say(f"full c2 N={wl.n_agents} E={wl.n_edges} K={wl.K}")
+    r = run_gpu(G, wl, mode=1, ckpt=10, target=tgt, backward=True)
+    ref = O.run_workload(wl, mode=O.HARD_ST, target=tgt, directions=O.standard_directions(wl.K, 8))
+    assert np.array_equal(r["counts"][0], ref["counts"])
+    assert np.array_equal(r["drm"][0], ref["drm"])
+    assert r["loss"][0] == pytest.approx(ref["loss"], rel=1e-12)
+    assert_grads(grad_vector(r), ref["dL"])
+
+
 # ---------------------------------------------------------------- gradients
 
 @pytest.fixture(scope="module")
