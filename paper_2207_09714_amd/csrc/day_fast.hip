@@ -1,6 +1,6 @@
-// Split day kernels (float state, one parameter set, one population, up to
-// 2^24 agents): a persistent neighbour-sum kernel and an element-wise agent
-// kernel.
+// Split day kernels (float state, one simulation -- one parameter set, or one
+// per packed population -- fewer than 2^24 agents): a persistent neighbour-sum
+// kernel and an element-wise agent kernel.
 //
 // Neighbour sum.  One 1024-thread block per compute unit; the gathered side
 // is a one-bit-per-agent mask held in LDS -- the infectious mask in the

@@ -20,7 +20,7 @@ constexpr uint32_t kDayInit = 0xFFFFFFFFu;
 // persistent kernels: one 1024-thread block per compute unit holding a
 // one-bit-per-agent mask in LDS
 constexpr int kFastBlock = 1024;
-constexpr int kFastMaskWords = 16384;  // 64-bit words of LDS mask: up to 2^20 agents
+constexpr int kFastMaskWords = 16384;  // 64-bit words of LDS mask: 2^20 agents (one sender slice)
 // The split B = 1 kernels read a sender-sliced copy of the contact list:
 // slice p holds the contacts whose sender lies in [p * 2^20, (p + 1) * 2^20),
 // so one slice's mask fits the LDS mask above.
