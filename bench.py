@@ -289,6 +289,108 @@ def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
     return out
 
 
+def er_directed_per_day(wl) -> int:
+    """Directed contacts per day of the daily random layer: round(n_p * mean / 2)
+    undirected pairs in each population of at least two agents, both ways."""
+    if not wl.er_mean_deg:
+        return 0
+    offs = wl.pop.pop_offsets
+    return 2 * sum(int(round(float(offs[p + 1] - offs[p]) * float(wl.er_mean_deg) / 2.0))
+                   for p in range(len(offs) - 1) if offs[p + 1] - offs[p] >= 2)
+
+
+def c1_leg(gabm, torch, steps: int, warmup: int):
+    """The plain forward of the 10,000-agent workload in double-precision
+    state (households plus the daily random layer, 30 days): a run is a few
+    hundred kilobytes per day, so it is launch-bound and reported in days/s,
+    eager and with each run captured in a hipGraph."""
+    from synth import make_workload
+
+    wl = make_workload("c1")
+    g = gabm.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, n_age=8,
+                   pop_offsets=wl.pop.pop_offsets, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight)
+    info = g.info()
+    E = info["n_edges"] + 2 * info["er_pairs_per_day"]
+    out = {"workload": f"c1: plain forward, {wl.n_agents} agents, {E} directed contacts per day "
+                       f"(households + daily random layer), {wl.K} days, f64 state",
+           "n_agents": wl.n_agents, "edges_per_day": E, "days": wl.K}
+    for launch in ("eager", "graph"):
+        sim = gabm.Simulator(g, K=wl.K, Z=wl.Z, mode=gabm.PLAIN, precision=gabm.F64,
+                             use_hip_graph=launch == "graph")
+        pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+        for _ in range(max(1, warmup)):
+            sim.forward(pb, seed=wl.seed)
+        torch.cuda.synchronize()
+        n = max(10, steps)
+        t0 = time.perf_counter()
+        for _ in range(n):
+            sim.forward(pb, seed=wl.seed)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / n
+        out[launch] = {"ms_per_run": dt * 1e3, "days_per_s": wl.K / dt, "edge_days_per_s": E * wl.K / dt}
+        del sim
+    return out
+
+
+def oracle_table():
+    """The oracle timed on this host, single thread: C1, C2, C3 and the packed
+    populations (C4b, population by population) in full, and 4 of the 128
+    simulations of the batched workload (C4a, scaled to 128).  Each in two
+    forms: the hard forward alone, and the forward with the 11 forward-mode
+    tangent directions that give the gradients (C1 is a plain-forward
+    workload).  Contacts per day include the daily random layer."""
+    import numpy as np
+
+    from oracle import oracle as ora
+    from synth import make_workload
+
+    ora.build()
+    rows = []
+    for name in ("c1", "c2", "c3", "c4b", "c4a"):
+        wl = make_workload(name)
+        K = wl.K
+        E = len(wl.src) + er_directed_per_day(wl)
+        dirs = ora.standard_directions(K, 8)
+        tgt = load_target(name, K)
+        tgt = np.zeros(K) if tgt is None else tgt
+        if name == "c4b":  # each population alone (they share no contacts)
+            offs = wl.pop.pop_offsets
+            parts = []
+            for p in range(len(offs) - 1):
+                lo, hi = int(offs[p]), int(offs[p + 1])
+                sel = (wl.dst >= lo) & (wl.dst < hi)
+                parts.append(dict(age=wl.pop.age[lo:hi], pop_offsets=np.array([0, hi - lo], np.int32),
+                                  src=wl.src[sel] - lo, dst=wl.dst[sel] - lo, w=wl.w[sel], R=wl.R[p], S=wl.S[p],
+                                  m=wl.m[p], i0=wl.i0[p], Z=wl.Z[p:p + 1], pop_id_base=p))
+            scale, sims = 1.0, f"{len(parts)} populations, one after another"
+        elif name == "c4a":  # 4 of the 128 simulations (sets 0-3, replicate 0), scaled
+            parts = [dict(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w,
+                          R=wl.R[k], S=wl.S[k], m=wl.m[k], i0=wl.i0[k], Z=wl.Z) for k in range(4)]
+            B = wl.n_sets * wl.n_reps
+            scale, sims = B / 4.0, f"4 of {B} simulations, time scaled by {B // 4}"
+        else:
+            parts = [dict(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w,
+                          R=wl.R[0], S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=wl.Z)]
+            scale, sims = 1.0, "1 simulation"
+        B_all = wl.n_sets * wl.n_reps if name == "c4a" else 1
+        row = {"workload": name, "n_agents": wl.n_agents, "edges_per_day": E, "days": K, "sims": sims}
+        forms = [("hard_forward", ora.PLAIN, None)]
+        if name != "c1":
+            forms.append(("forward_with_tangents", ora.HARD_ST, dirs))
+        for form, mode, d in forms:
+            t0 = time.perf_counter()
+            for i, q in enumerate(parts):
+                ora.run(K=K, T=wl.T, tau_E=wl.tau_E, tau_I=wl.tau_I, mode=mode, tau_g=wl.tau_g, seed=wl.seed,
+                        er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=tgt, directions=d, **q)
+                if len(parts) > 1:
+                    note(f"oracle {name} {form}: part {i + 1} of {len(parts)} done")
+            dt = (time.perf_counter() - t0) * scale
+            row[form] = {"s": dt, "edge_days_per_s": E * K * B_all / dt, "days_per_s": K * B_all / dt}
+            note(f"oracle {name} {form}: {dt:.1f} s")
+        rows.append(row)
+    return {"oracle_table": rows, "cores": 1, "host_nproc": os.cpu_count()}
+
+
 def note(msg: str) -> None:
     """Progress line on stderr (stdout carries only the JSON result)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -300,6 +402,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4b", "c5"])
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="time the oracle on this host for every workload (several minutes; no GPU) and exit")
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="launches one by one with HIP events around every kernel (default), or the day loops "
                          "captured in hipGraphs (no per-kernel timing)")
@@ -331,6 +435,10 @@ def main():
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
+
+    if args.oracle_table:
+        print(json.dumps(oracle_table()), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -428,6 +536,9 @@ def main():
 
     if args.only is None and not args.no_batched:
         res["batched"] = batched_legs(gabm, torch, max(1, args.steps // 2), max(1, args.warmup), eager)
+    if args.only is None:
+        res["c1"] = c1_leg(gabm, torch, args.steps, args.warmup)
+        note(f"c1 plain forward (f64): {res['c1']['graph']['ms_per_run']:.3f} ms per run with hipGraphs")
 
     if args.only is not None:
         print(json.dumps({k: v for k, v in res.items()}), flush=True)
@@ -506,6 +617,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_days)
     if "batched" in res:
         out["batched"] = res["batched"]
+    if "c1" in res:
+        out["c1_plain_f64"] = res["c1"]
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
                             "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
     print(json.dumps(out), flush=True)
