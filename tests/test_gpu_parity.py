@@ -484,18 +484,20 @@ def test_full_size_c4b_sampled(G, O):
 @pytest.mark.timeout(300)
 def test_full_size_c2(G, O):
     """The full 100k-agent workload with its daily random layer (60 days,
-    checkpoint every 10 days, the stored target): trajectory equal to the
-    oracle's, gradients equal to the oracle's forward-mode tangents."""
+    checkpoint every 10 days, the stored target), eager and with each run
+    captured in a hipGraph: trajectory equal to the oracle's, gradients equal
+    to the oracle's forward-mode tangents."""
     gold = _golden()
     wl = make_workload("c2")
     tgt = gold.read_target("c2")[: wl.K]
-    _say(f"full c2 N={wl.n_agents} E={wl.n_edges} K={wl.K}")
-    r = run_gpu(G, wl, mode=1, ckpt=10, target=tgt, backward=True)
     ref = O.run_workload(wl, mode=O.HARD_ST, target=tgt, directions=O.standard_directions(wl.K, 8))
-    assert np.array_equal(r["counts"][0], ref["counts"])
-    assert np.array_equal(r["drm"][0], ref["drm"])
-    assert r["loss"][0] == pytest.approx(ref["loss"], rel=1e-12)
-    assert_grads(grad_vector(r), ref["dL"])
+    for hip_graph in (False, True):
+        _say(f"full c2 N={wl.n_agents} E={wl.n_edges} K={wl.K} hip_graph={hip_graph}")
+        r = run_gpu(G, wl, mode=1, ckpt=10, target=tgt, backward=True, hip_graph=hip_graph)
+        assert np.array_equal(r["counts"][0], ref["counts"]), hip_graph
+        assert np.array_equal(r["drm"][0], ref["drm"]), hip_graph
+        assert r["loss"][0] == pytest.approx(ref["loss"], rel=1e-12)
+        assert_grads(grad_vector(r), ref["dL"])
 
 
 # ---------------------------------------------------------------- gradients
