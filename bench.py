@@ -454,7 +454,7 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
     if args.oracle_table:

@@ -52,7 +52,7 @@ typedef enum {
   GABM_EHIP = 3,         /* a HIP runtime call failed */
   GABM_ENOTSYM = 4,      /* contact list is not symmetric */
   GABM_ERANGE = 5,       /* an index or size is out of range */
-  GABM_EUNSUPPORTED = 6, /* valid but not supported by this build */
+  GABM_EUNSUPPORTED = 6, /* valid but not supported by this library */
   GABM_ESTATE = 7        /* call order violated (e.g. backward before forward) */
 } gabm_status;
 
@@ -327,7 +327,7 @@ typedef struct {
 gabm_status gabm_sim_kernel_times(gabm_sim s, gabm_kernel_times *out, int32_t reset);
 
 /* Autotuner for the kernel schedule (gabm_run_desc.schedule): for every
- * schedule of this build (GABM_N_SCHEDULES), creates a temporary simulation
+ * schedule of the library (GABM_N_SCHEDULES), creates a temporary simulation
  * of the run (p, run) with that schedule, times `days` forward days of it on
  * `stream` (HIP events, after a warm-up day), and returns in *best a copy of
  * *run with the fastest schedule.  ms_per_day (host, GABM_N_SCHEDULES

@@ -1,4 +1,4 @@
-// Run driver: allocation of a simulation, the K-day forward with state
+// Run loop: allocation of a simulation, the K-day forward with state
 // snapshots every `ckpt` days, and the reverse pass that replays each
 // segment from its snapshot before walking it backwards (the loop over days
 // is unrolled by hand instead of being kept whole in memory, which is what
@@ -669,7 +669,7 @@ static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st
   fill0(s.gi0, (size_t)s.n_sets * kSlots * 8, st);
 }
 
-// ---------------------------------------------------------------- generic driver
+// ---------------------------------------------------------------- day loops of a run
 
 template <typename RT>
 static void run_forward(Sim& s, const DParams& P, Rng rng, uint32_t stream, const double* target, int stride,
@@ -719,7 +719,7 @@ static void run_backward(Sim& s, const DParams& P, Rng rng, uint32_t stream, con
   fin_bwd(s, out, st);
 }
 
-// captured or direct execution of a driver function
+// captured or direct execution of a run function
 template <class F>
 static gabm_status execute(Sim& s, bool fwd, const void* k1, const void* k2, const void* k3, const void* k4,
                            const void* k5, const void* k6, hipStream_t st, F f) {
