@@ -391,27 +391,6 @@ def oracle_table():
     return {"oracle_table": rows, "cores": 1, "host_nproc": os.cpu_count()}
 
 
-def copy_leg(torch, reps: int = 20):
-    """A STREAM-like device copy (1 GiB read + 1 GiB written per copy): the
-    HBM bandwidth a plain streaming kernel reaches on this GPU, as context for
-    the roofline fraction (which is taken against the 8 TB/s specification)."""
-    n = (1 << 30) // 4
-    x = torch.ones(n, dtype=torch.float32, device="cuda")
-    y = torch.empty_like(x)
-    for _ in range(3):
-        y.copy_(x)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        y.copy_(x)
-    e1.record()
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    del x, y
-    return {"bytes_per_copy": 8 * n, "ms_per_copy": ms, "GBps": 8 * n / (ms * 1e-3) / 1e9,
-            "kernel": "torch copy_ (rocclr copy kernel)"}
-
-
 def note(msg: str) -> None:
     """Progress line on stderr (stdout carries only the JSON result)."""
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -558,8 +537,6 @@ def main():
     if args.only is None and not args.no_batched:
         res["batched"] = batched_legs(gabm, torch, max(1, args.steps // 2), max(1, args.warmup), eager)
     if args.only is None:
-        res["copy"] = copy_leg(torch)
-        note(f"device copy: {res['copy']['GBps']:.0f} GB/s")
         res["c1"] = c1_leg(gabm, torch, args.steps, args.warmup)
         note(f"c1 plain forward (f64): {res['c1']['graph']['ms_per_run']:.3f} ms per run with hipGraphs")
 
@@ -636,17 +613,12 @@ def main():
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "traffic": read_traffic(kname, wl.name),
                            "alg_bytes_per_launch": d["alg_bytes_per_launch"], "avg_launch_ms": d["avg_ms"]}
-        if "copy" in res:
-            out["roofline"]["copy_GBps"] = res["copy"]["GBps"]
-            out["roofline"]["frac_of_copy"] = achieved / res["copy"]["GBps"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_days)
     if "batched" in res:
         out["batched"] = res["batched"]
     if "c1" in res:
         out["c1_plain_f64"] = res["c1"]
-    if "copy" in res:
-        out["hbm_copy"] = res["copy"]
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
                             "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
     print(json.dumps(out), flush=True)
