@@ -262,12 +262,17 @@ def batched_legs(gabm, torch, steps: int, warmup: int, eager: bool):
         torch.cuda.synchronize()
         if eager:
             sim.kernel_times(reset=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(steps):
+        evs[0].record()
+        for k in range(steps):
             step()
+            evs[k + 1].record()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / steps
-        leg = {"ms_per_run": dt * 1e3, "value": E * K * B / dt, "unit": "edge-days/s", "sim_days_per_s": K * B / dt}
+        per = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(steps))
+        leg = {"ms_per_run": dt * 1e3, "median_ms_per_run": per[len(per) // 2], "value": E * K * B / dt,
+               "unit": "edge-days/s", "sim_days_per_s": K * B / dt}
         if eager:
             kt = sim.kernel_times(reset=True)
             leg["kernels"] = {}
@@ -491,13 +496,22 @@ def main():
         torch.cuda.synchronize()
         if timing:
             sim.kernel_times(reset=True)
+        # one event between consecutive steps on the library's stream (torch's
+        # current stream) gives per-step device times for the median
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        evs[0].record()
+        for k in range(args.steps):
             step()
+            evs[k + 1].record()
         torch.cuda.synchronize()
-        return (time.perf_counter() - t0) / args.steps
+        dt = (time.perf_counter() - t0) / args.steps
+        per = sorted(evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps))
+        medians.append(per[len(per) // 2])
+        return dt
 
     res = {}
+    medians = []
     # kernel schedule picked by the library's autotuner (a few timed forward days per schedule)
     pp = dict(n_sets=wl.n_sets, per_pop_params=wl.per_pop_params)
     sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST, **pp,
@@ -512,6 +526,7 @@ def main():
                              time_kernels=TIME_EVERY if eager else 0, tau_g=wl.tau_g, schedule=sched)
         pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
         res["diff_s"] = timed(sim, pb, True, eager)
+        res["diff_median_ms"] = medians[-1]
         res["kt"] = sim.kernel_times(reset=True) if eager else None
         res["loss"] = float(sim.loss[0].item())
         res["grad_R"] = float(sim.dR[0].sum().item())
@@ -530,6 +545,7 @@ def main():
                               time_kernels=TIME_EVERY if eager else 0, schedule=sched)
         pbp = simp.params(wl.R, wl.S, wl.m, wl.i0)
         res["plain_s"] = timed(simp, pbp, False, eager)
+        res["plain_median_ms"] = medians[-1]
         note(f"plain forward: {res['plain_s'] * 1e3:.2f} ms per run")
         res["kt_plain"] = simp.kernel_times(reset=True) if eager else None
         del simp
@@ -554,6 +570,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": res["diff_s"] * 1e3,
+        "median_ms_per_step": res["diff_median_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -571,7 +588,7 @@ def main():
         },
         "days_per_s": K / res["diff_s"],
         "plain_fwd": {"value": edge_days / res["plain_s"], "unit": "edge-days/s", "ms_per_run": res["plain_s"] * 1e3,
-                      "days_per_s": K / res["plain_s"]},
+                      "median_ms_per_run": res["plain_median_ms"], "days_per_s": K / res["plain_s"]},
         "loss": res["loss"],
         "workspace_bytes": res["workspace_bytes"],
         "graph_gen_s": gen_s,
