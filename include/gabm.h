@@ -229,7 +229,8 @@ typedef struct {
                           than 2^24 agents (one LDS mask per slice of 2^20 senders), one
                           parameter set or one per packed population; B > 32: one wave per
                           tile with 64-contact windows);
-                          1: receiver-tile kernels (B = 1) / lane-group kernels (B > 1) only.
+                          1: receiver-tile kernels (B = 1) / lane-group kernels (B > 1) only;
+                          any other value: GABM_EINVAL.
                           gabm_autotune picks between them by measurement. */
   int32_t time_kernels; /* k > 0: record HIP events around every k-th launch of each class of day
                            kernel (eager launches only; see gabm_sim_kernel_times); 0: off */

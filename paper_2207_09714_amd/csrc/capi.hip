@@ -388,6 +388,7 @@ static gabm_status check_run(const Graph& G, const gabm_params* p, const gabm_ru
   GABM_CHECK(run->ckpt_every >= 0, GABM_EINVAL, "ckpt_every must be >= 0");
   GABM_CHECK(run->precision == GABM_F32 || run->precision == GABM_F64, GABM_EINVAL, "unknown precision");
   GABM_CHECK(run->time_kernels >= 0, GABM_EINVAL, "time_kernels must be >= 0");
+  GABM_CHECK(run->schedule == 0 || run->schedule == 1, GABM_EINVAL, "schedule must be 0 or 1");
   const int64_t B = p->per_pop_params ? run->n_reps : (int64_t)p->n_sets * run->n_reps;
   if (B > 1) {
     GABM_CHECK(B <= kBMaxB, GABM_EUNSUPPORTED, "a batched run takes at most 256 simulations");

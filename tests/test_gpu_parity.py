@@ -126,6 +126,11 @@ def test_symmetrize_and_errors(G):
     with pytest.raises(L.GabmError) as e:
         G.Graph(n_agents=n, src=[0, 1], dst=[1, 0], age=bad_age)
     assert e.value.code == L.ERANGE
+    # run descriptions are checked on the host before any allocation
+    for kw in (dict(schedule=2), dict(schedule=-1), dict(ckpt_every=-1), dict(n_reps=0)):
+        with pytest.raises(L.GabmError) as e:
+            G.Simulator(g1, K=4, Z=[1.0], mode=G.HARD_ST, **kw)
+        assert e.value.code == L.EINVAL, kw
 
 
 def test_daily_random_pairs_bit_exact(G, O):
