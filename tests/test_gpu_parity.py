@@ -514,6 +514,49 @@ def grad_case():
     return wl, tgt
 
 
+def test_relaxed_gradients_match_central_differences(G):
+    """In the relaxed mode (every sample a binary-concrete value, so the loss
+    is smooth in the parameters) with double-precision state, the adjoint
+    gradients of the deaths loss with respect to R on one day, the
+    susceptibility of one age group, the mortality rate and the initial
+    infected fraction equal central differences of the library's own loss at
+    the same Philox seed (households, workplaces and the daily random layer)."""
+    wl = make_workload("c2", n_agents=3000, K=20)
+    _say(f"relaxed gradients vs central differences N={wl.n_agents} K={wl.K}")
+    g = graph_of(G, wl)
+    t = torch.tensor(np.linspace(0.0, 0.3, wl.K), device="cuda")
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.SOFT, precision=G.F64, ckpt_every=5, tau_g=wl.tau_g)
+    base = dict(R=wl.R.astype(np.float32).copy(), S=wl.S.astype(np.float32).copy(),
+                m=wl.m.astype(np.float32).copy(), i0=wl.i0.astype(np.float32).copy())
+
+    def loss(p):
+        out = sim.forward(sim.params(p["R"], p["S"], p["m"], p["i0"]), seed=wl.seed, target=t)
+        return float(out["loss"][0].item())
+
+    pb = sim.params(base["R"], base["S"], base["m"], base["i0"])
+    sim.forward(pb, seed=wl.seed, target=t)
+    gr = {k: v.cpu().numpy().copy() for k, v in sim.backward(pb, seed=wl.seed).items()}
+    # R on day 3: infections that day can still die before the horizon
+    cases = [("R", (0, 3), gr["dR"][0, 3]), ("S", (0, 3), gr["dS"][0, 3]), ("m", (0,), gr["dm"][0]),
+             ("i0", (0,), gr["di0"][0])]
+    got, fd = [], []
+    for name, idx, adj in cases:
+        x = float(base[name][idx])
+        vals = []
+        for sign in (1.0, -1.0):
+            p = {k: v.copy() for k, v in base.items()}
+            p[name][idx] = np.float32(x * (1.0 + sign * 2.0**-9))
+            vals.append((loss(p), float(p[name][idx])))
+        (lp, xp), (lm, xm) = vals
+        got.append(adj)
+        fd.append((lp - lm) / (xp - xm))
+    got, fd = np.array(got), np.array(fd)
+    _say(f"adjoint {got} central differences {fd}")
+    assert np.all(fd != 0.0), fd
+    scale = np.maximum(np.abs(fd), 1e-3 * np.max(np.abs(fd)))
+    assert np.all(np.abs(got - fd) <= 1e-4 * scale), (got, fd)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_straight_through_gradients(G, O, grad_case, precision):
     wl, tgt = grad_case
