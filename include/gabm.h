@@ -167,7 +167,10 @@ typedef struct {
 /* Infectiousness formats for gabm_transmit_fwd. */
 enum { GABM_INF_REC = 0,   /* gabm_rec[N]: T[stage] */
        GABM_INF_F32 = 1,   /* float[N] */
-       GABM_INF_F64 = 2 }; /* double[N] */
+       GABM_INF_F64 = 2,   /* double[N] */
+       GABM_INF_BIT1 = 3 }; /* uint64_t[ceil(N/64)]: bit (c & 63) of word c >> 6 set when agent c is
+                               infectious; value T[I] for a set bit, 0 otherwise (one bit cannot tell
+                               exposed agents apart, so T[E] is not applied) */
 
 /* Transmit (Eq. 3 argument): A_i = sum over the static contacts j->i of
  * w * inf_j, plus the day's random layer (when the graph has one), and

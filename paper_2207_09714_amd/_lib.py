@@ -18,7 +18,7 @@ STATUS_NAMES = {0: "GABM_OK", 1: "GABM_EINVAL", 2: "GABM_ENOMEM", 3: "GABM_EHIP"
 PLAIN, HARD_ST, SOFT = 0, 1, 2
 F32, F64 = 0, 1
 SYMMETRIZE, CHECK_SYMMETRIC = 1, 2
-INF_REC, INF_F32, INF_F64 = 0, 1, 2
+INF_REC, INF_F32, INF_F64, INF_BIT1 = 0, 1, 2, 3
 TAG_INIT, TAG_INFECT, TAG_MORT, TAG_ER = 0, 1, 2, 3
 
 EXPORTS = (

@@ -61,6 +61,7 @@ struct StepInf {
   __device__ __forceinline__ double at(int c) const {
     if (fmt == GABM_INF_F32) return (double)((const float*)v)[c];
     if (fmt == GABM_INF_F64) return ((const double*)v)[c];
+    if (fmt == GABM_INF_BIT1) return ((((const unsigned long long*)v)[c >> 6] >> (c & 63)) & 1ull) ? TI : 0.0;
     const uint32_t st = rec_stage(((const uint32_t*)v)[c]);
     return st == ST_I ? TI : (st == ST_E ? TE : 0.0);
   }
@@ -279,7 +280,8 @@ gabm_status gabm_graph_destroy(gabm_graph g) {
 gabm_status gabm_transmit_fwd(gabm_graph g, const void* inf, int32_t fmt, const gabm_params* p, int32_t set,
                               const gabm_rng* rng, int32_t day, double* A, double* lambda, void* stream) {
   GABM_CHECK(g && inf && A && rng, GABM_EINVAL, "graph, inf, A or rng is NULL");
-  GABM_CHECK(fmt == GABM_INF_REC || fmt == GABM_INF_F32 || fmt == GABM_INF_F64, GABM_EINVAL, "unknown inf format");
+  GABM_CHECK(fmt == GABM_INF_REC || fmt == GABM_INF_F32 || fmt == GABM_INF_F64 || fmt == GABM_INF_BIT1, GABM_EINVAL,
+             "unknown inf format");
   const Graph& G = g->g;
   DParams P;
   gabm_status rc = check_params(G, p, &P);

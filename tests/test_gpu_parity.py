@@ -177,6 +177,14 @@ def test_single_steps_match_oracle(G, O):
         G.transmit_fwd(g, inf, 1, pb, 0, rng, t, A2)
         G.transmit_fwd(g, inf.double(), 2, pb, 0, rng, t, A)
         assert torch.equal(A, A2) and np.array_equal(A.cpu().numpy(), ref["A"][t])
+        # one bit per agent (the workload has T[E] = 0)
+        by = np.packbits(ref["stage"][t] == 2, bitorder="little")
+        words = np.zeros(((N + 63) // 64) * 8, np.uint8)
+        words[: len(by)] = by
+        bits = torch.tensor(words.view(np.int64), device="cuda")
+        A2.zero_()
+        G.transmit_fwd(g, bits, 3, pb, 0, rng, t, A2)
+        assert torch.equal(A, A2)
 
     # adjoint of the neighbour sum: a gather over the transpose (dense check)
     gv = torch.tensor(np.random.default_rng(1).standard_normal(N), device="cuda")
