@@ -337,8 +337,8 @@ def c1_leg(gabm, torch, steps: int, warmup: int):
     return out
 
 
-def oracle_table():
-    """The oracle timed on this host, single thread: C1, C2, C3 and the packed
+def cpu_baseline_table():
+    """The cpu_baseline leg over every workload: the oracle timed on this host, single thread: C1, C2, C3 and the packed
     populations (C4b, population by population) in full, and 4 of the 128
     simulations of the batched workload (C4a, scaled to 128).  Each in two
     forms: the hard forward alone, and the forward with the 11 forward-mode
@@ -393,7 +393,7 @@ def oracle_table():
             row[form] = {"s": dt, "edge_days_per_s": E * K * B_all / dt, "days_per_s": K * B_all / dt}
             note(f"oracle {name} {form}: {dt:.1f} s")
         rows.append(row)
-    return {"oracle_table": rows, "cores": 1, "host_nproc": os.cpu_count()}
+    return {"cpu_baseline_table": rows, "kind": "oracle", "cores": 1, "host_nproc": os.cpu_count()}
 
 
 def note(msg: str) -> None:
@@ -407,8 +407,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4b", "c5"])
-    ap.add_argument("--oracle-table", action="store_true",
-                    help="time the oracle on this host for every workload (several minutes; no GPU) and exit")
+    ap.add_argument("--cpu-baseline-table", action="store_true",
+                    help="the cpu_baseline leg for every workload: time the oracle on this host (several minutes; "
+                         "no GPU) and exit")
     ap.add_argument("--launch", default="eager", choices=["eager", "graph"],
                     help="launches one by one with HIP events around every kernel (default), or the day loops "
                          "captured in hipGraphs (no per-kernel timing)")
@@ -441,8 +442,8 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported"}))
         sys.exit(2)
 
-    if args.oracle_table:
-        print(json.dumps(oracle_table()), flush=True)
+    if args.cpu_baseline_table:
+        print(json.dumps(cpu_baseline_table()), flush=True)
         return
 
     import numpy as np
