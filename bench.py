@@ -337,6 +337,37 @@ def c1_leg(gabm, torch, steps: int, warmup: int):
     return out
 
 
+def calibration_leg(gabm, torch, wl, g, sched, steps: int = 5):
+    """C-GradABM on the headline workload: Adam on the weekly reproduction
+    numbers (13 blocks for 90 days), S, m and i0 against the stored deaths
+    target, from R = 2.0; each update is one forward+backward run with
+    checkpoints plus the optimiser step.  The timed call makes `steps`
+    updates and one closing forward."""
+    import numpy as np
+
+    from paper_2207_09714_amd import calibrate as C
+
+    tgt = load_target(wl.name, wl.K)
+    if tgt is None:
+        return None
+    sim = gabm.Simulator(g, K=wl.K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=wl.ckpt_every, tau_g=wl.tau_g,
+                         schedule=sched)
+    R0 = np.full((1, wl.K), 2.0, np.float32)
+    kw = dict(lr=0.05, period=7, optimizer="adam", seed=wl.seed)
+    C.calibrate(sim, tgt, R0, wl.S, wl.m, wl.i0, steps=1, **kw)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = C.calibrate(sim, tgt, R0, wl.S, wl.m, wl.i0, steps=steps, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"workload": f"{wl.name}: Adam on weekly R, S, m, i0 against the stored deaths target",
+            "updates": steps, "s": dt, "ms_per_update": dt / steps * 1e3,
+            "note": "each update: forward+backward with checkpoint recomputation and the Adam step; the timed "
+                    "call also runs one closing forward",
+            "loss_first": res.loss[0], "loss_last": res.loss[-1],
+            "R_blocks": [round(float(x), 4) for x in res.R_blocks[0].cpu()]}
+
+
 def cpu_baseline_table():
     """The cpu_baseline leg over every workload: the oracle timed on this host, single thread: C1, C2, C3 and the packed
     populations (C4b, population by population) in full, and 4 of the 128
@@ -554,6 +585,10 @@ def main():
     if args.only is None and not args.no_batched:
         res["batched"] = batched_legs(gabm, torch, max(1, args.steps // 2), max(1, args.warmup), eager)
     if args.only is None:
+        res["calibration"] = calibration_leg(gabm, torch, wl, g, sched)
+        if res["calibration"]:
+            note(f"calibration: {res['calibration']['ms_per_update']:.1f} ms per update, loss "
+                 f"{res['calibration']['loss_first']:.4g} -> {res['calibration']['loss_last']:.4g}")
         res["c1"] = c1_leg(gabm, torch, args.steps, args.warmup)
         note(f"c1 plain forward (f64): {res['c1']['graph']['ms_per_run']:.3f} ms per run with hipGraphs")
 
@@ -637,6 +672,8 @@ def main():
         out["batched"] = res["batched"]
     if "c1" in res:
         out["c1_plain_f64"] = res["c1"]
+    if res.get("calibration"):
+        out["calibration"] = res["calibration"]
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
                             "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
     print(json.dumps(out), flush=True)

@@ -1,0 +1,116 @@
+"""GPU tests of the C-GradABM calibration loop (Section 3.2; the C- variant of
+Section 4): one plain gradient-descent step of each parameter group equals
+the paper's update rule applied with the oracle's gradient (per-week
+reproduction numbers, per-age susceptibilities, mortality, initial infected
+fraction), and an Adam fit of the weekly reproduction number to a target the
+simulator produced at a known value recovers that value."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from synth import make_workload  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2207_09714_amd import gabm
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return gabm
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle
+
+    return oracle
+
+
+def graph_of(G, wl):
+    return G.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, n_age=8,
+                   pop_offsets=wl.pop.pop_offsets, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight)
+
+
+def block_directions(K, period, n_age):
+    """Oracle tangent directions: one per block of R (its days together), then
+    S[0..n_age-1], m and i0."""
+    nb = (K + period - 1) // period
+    nd = nb + n_age + 2
+    dR = np.zeros((nd, K))
+    dS = np.zeros((nd, n_age))
+    dm = np.zeros(nd)
+    di0 = np.zeros(nd)
+    for b in range(nb):
+        dR[b, b * period:(b + 1) * period] = 1.0
+    for a in range(n_age):
+        dS[nb + a, a] = 1.0
+    dm[nb + n_age] = 1.0
+    di0[nb + n_age + 1] = 1.0
+    return (dR, dS, dm, di0), nb
+
+
+def test_gradient_step_matches_oracle_rule(G, O):
+    """theta_1 = theta_0 - alpha dL/dtheta with the oracle's gradient, for each
+    parameter group on its own (weekly R blocks on a 21-day run, S, m, i0),
+    straight-through mode, the daily random layer included."""
+    from paper_2207_09714_amd import calibrate as C
+
+    import copy
+
+    wl = copy.copy(make_workload("c2", n_agents=5000, K=21))
+    wl.S = (0.8 * wl.S).astype(np.float32)  # every S below 0.8: the step stays inside (0, 1]
+    tgt = np.linspace(0.0, 0.6, wl.K)
+    _say(f"calibration step vs oracle N={wl.n_agents} K={wl.K}")
+    dirs, nb = block_directions(wl.K, 7, 8)
+    # the start: R constant within each week (the block means are the values)
+    R0 = np.repeat(np.array([2.4, 2.6, 2.8], np.float32), 7)[None, :]
+    ref = O.run_workload(wl, mode=O.HARD_ST, R=R0[0], target=tgt, directions=dirs)
+    gref = {"R": ref["dL"][:nb], "S": ref["dL"][nb:nb + 8], "m": ref["dL"][nb + 8:nb + 9],
+            "i0": ref["dL"][nb + 9:nb + 10]}
+    start = {"R": R0[0, ::7], "S": wl.S[0], "m": wl.m, "i0": wl.i0}
+    g = graph_of(G, wl)
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.HARD_ST, ckpt_every=7, tau_g=wl.tau_g)
+    for name in ("R", "S", "m", "i0"):
+        want = gref[name]
+        theta0 = np.asarray(start[name], np.float64)
+        # a step of about 1% of the parameter
+        lr = 0.01 * float(np.mean(np.abs(theta0))) / float(np.max(np.abs(want)))
+        res = C.calibrate(sim, tgt, R0, wl.S, wl.m, wl.i0, steps=1, lr=lr, period=7, optimizer="gd",
+                          seed=wl.seed, fit=(name,))
+        theta1 = {"R": res.R_blocks[0], "S": res.S[0], "m": res.m, "i0": res.i0}[name].cpu().numpy()
+        got = (theta0 - theta1.astype(np.float64)) / lr
+        scale = np.maximum(np.abs(want), 1e-3 * np.max(np.abs(want)))
+        # float32 parameters: the step is resolved to ~1e-5 of itself
+        assert np.all(np.abs(got - want) <= 1e-4 * scale + 2e-5 * np.max(np.abs(want))), (name, got, want)
+        assert res.loss[0] == pytest.approx(ref["loss"], rel=1e-12)
+
+
+def test_adam_fit_recovers_weekly_reproduction_number(G):
+    """Relaxed mode (smooth loss): the target is the simulator's own deaths at
+    R = 3.0 in every week with the same seed; starting from R = 2.0, Adam on
+    the weekly R blocks lowers the loss by more than 20x and brings the first
+    week's R, which shapes the deaths most, within 5% of 3.0."""
+    from paper_2207_09714_amd import calibrate as C
+
+    wl = make_workload("c2", n_agents=5000, K=21)
+    _say(f"Adam calibration N={wl.n_agents} K={wl.K}")
+    g = graph_of(G, wl)
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.SOFT, ckpt_every=7, tau_g=wl.tau_g)
+    Rstar = np.full((1, wl.K), 3.0, np.float32)
+    out = sim.forward(sim.params(Rstar, wl.S, wl.m, wl.i0), seed=wl.seed)
+    tgt = out["deaths"][0].clone()
+    R0 = np.full((1, wl.K), 2.0, np.float32)
+    res = C.calibrate(sim, tgt, R0, wl.S, wl.m, wl.i0, steps=60, lr=0.05, period=7, optimizer="adam",
+                      seed=wl.seed, fit=("R",))
+    _say(f"loss {res.loss[0]:.4g} -> {res.loss[-1]:.4g}; R blocks {res.R_blocks[0].cpu().numpy()}")
+    assert res.loss[-1] < res.loss[0] / 20.0
+    assert abs(float(res.R_blocks[0, 0]) - 3.0) < 0.15
+    assert torch.equal(res.R[0, :7], res.R_blocks[0, 0].expand(7))
