@@ -177,6 +177,8 @@ int ora_run(const ora_cfg *c, ora_out *o) {
 
   const double TE = c->T[ORA_E], TI = c->T[ORA_I];
   const double m = c->m, i0 = c->i0, tau = c->tau_g;
+  /* weight of the k-th day after exposure (k = 1..W): the profile value, 1 when flat */
+#define IOTA(k) (c->iota ? (double)c->iota[(k) - 1] : 1.0)
 
   ws_t ws;
   memset(&ws, 0, sizeof ws);
@@ -277,20 +279,23 @@ int ora_run(const ora_cfg *c, ora_out *o) {
   for (int32_t t = 0; t < K; ++t) {
     /* ---- infectiousness of each agent at the start of day t ---- */
     for (int32_t j = 0; j < n; ++j) {
-      double wE = 0.0, wI = 0.0;
+      /* wE, wI: exposures still in the E / I window; pE, pI: the same weighted by the profile */
+      double wE = 0.0, wI = 0.0, pE = 0.0, pI = 0.0;
       for (int32_t k = 1; k <= W; ++k) {
         int32_t u = t - k;
         if (u < 0) break;
         double xv = ws.xi[(size_t)(u % W) * n + j];
-        if (k <= tE) wE += xv; else wI += xv;
+        if (k <= tE) { wE += xv; pE += IOTA(k) * xv; } else { wI += xv; pI += IOTA(k) * xv; }
       }
-      if (t < tI) wI += ws.x0[j];
+      if (t < tI) { wI += ws.x0[j]; pI += IOTA(t + tE + 1) * ws.x0[j]; }
       double win = TE * wE + TI * wI;
+      double pwin = TE * pE + TI * pI;
       if (mode == ORA_SOFT) {
-        ws.inf[j] = win;
+        ws.inf[j] = pwin;
       } else {
         double st = (double)c->T[ws.stage[j]];
-        ws.inf[j] = st;
+        /* hard: one exposure at most is in the window, so pwin = T[stage] * iota(k) */
+        ws.inf[j] = c->iota ? pwin : st;
         if (st != win) ++mismatch;
       }
       for (int32_t d = 0; d < nd; ++d) {
@@ -299,10 +304,10 @@ int ora_run(const ora_cfg *c, ora_out *o) {
         for (int32_t k = 1; k <= W; ++k) {
           int32_t u = t - k;
           if (u < 0) break;
-          double xv = dx[(size_t)(u % W) * n + j];
+          double xv = IOTA(k) * dx[(size_t)(u % W) * n + j];
           if (k <= tE) dE += xv; else dI += xv;
         }
-        if (t < tI) dI += ws.dx0[(size_t)d * n + j];
+        if (t < tI) dI += IOTA(t + tE + 1) * ws.dx0[(size_t)d * n + j];
         ws.dinf[(size_t)d * n + j] = TE * dE + TI * dI;
       }
     }
@@ -398,6 +403,7 @@ int ora_run(const ora_cfg *c, ora_out *o) {
     SNAPSHOT(t + 1);
   }
 #undef SNAPSHOT
+#undef IOTA
   *o->loss = loss / (double)K;
   if (o->mismatch) *o->mismatch = mismatch;
   free(dx0sum);

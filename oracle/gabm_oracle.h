@@ -59,6 +59,9 @@ typedef struct {
   const double *dS;           /* [ndir*n_age] */
   const double *dm;           /* [ndir] */
   const double *di0;          /* [ndir] */
+  const float *iota;          /* [tau_E + tau_I] infectiousness profile over days since exposure, or NULL
+                                 (flat): an agent exposed on day u contributes T[stage] * iota[t - u - 1]
+                                 on day t; an initial infection counts as exposed on day -tau_E - 1 */
 } ora_cfg;
 
 typedef struct {

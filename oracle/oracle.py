@@ -39,6 +39,7 @@ class _Cfg(C.Structure):
         ("m", C.c_float), ("i0", C.c_float), ("tau_g", C.c_float), ("Z", C.c_void_p),
         ("seed", C.c_uint64), ("stream", C.c_uint32), ("target", C.c_void_p),
         ("ndir", C.c_int32), ("dR", C.c_void_p), ("dS", C.c_void_p), ("dm", C.c_void_p), ("di0", C.c_void_p),
+        ("iota", C.c_void_p),
     ]
 
 
@@ -106,8 +107,12 @@ def standard_directions(K: int, n_age: int):
 
 def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), tau_E=3, tau_I=5,
         mode=PLAIN, tau_g=0.5, seed=0, stream=0, pop_id_base=0, er_mean_deg=0.0, er_weight=0.0,
-        target=None, directions=None, want_agents=False, want_stage=False):
+        target=None, directions=None, want_agents=False, want_stage=False, iota=None):
     """Run one simulation.  Parameters are float32 values (widened exactly).
+
+    ``iota`` = infectiousness profile over days since exposure ([tau_E +
+    tau_I], float32; None = flat): an agent exposed on day u contributes
+    T[stage] * iota[t - u - 1] on day t.
 
     ``directions`` = (dR[nd,K], dS[nd,n_age], dm[nd], di0[nd]) or None.
     Returns a dict with counts [K+1,5], drm [K], deaths [K], loss, and when
@@ -134,6 +139,12 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
     cfg.m, cfg.i0, cfg.tau_g, cfg.Z = float(np.float32(m)), float(np.float32(i0)), float(np.float32(tau_g)), _p(Zv)
     cfg.seed, cfg.stream, cfg.target = int(seed), int(stream), _p(tg)
     keep = [age, offs, src, dst, w, Rv, Sv, Tv, Zv, tg]
+    if iota is not None:
+        iv = np.ascontiguousarray(iota, np.float32).reshape(-1)
+        if iv.shape[0] != tau_E + tau_I:
+            raise ValueError("iota needs tau_E + tau_I values")
+        cfg.iota = _p(iv)
+        keep.append(iv)
     nd = 0
     if directions is not None:
         dR, dS, dm, di0 = (np.ascontiguousarray(x, np.float64) for x in directions)
@@ -163,7 +174,7 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
 
 
 def run_workload(wl, *, mode=None, set_index=0, stream=0, seed=None, R=None, target=None, directions=None,
-                 want_agents=False, want_stage=False, pop_index=None):
+                 want_agents=False, want_stage=False, pop_index=None, iota=None):
     """Run a ``synth`` workload on the oracle (one simulation).  For packed
     populations pass ``pop_index`` to simulate that population alone with its
     own parameter set (populations do not share contacts)."""
@@ -178,10 +189,10 @@ def run_workload(wl, *, mode=None, set_index=0, stream=0, seed=None, R=None, tar
                    tau_I=wl.tau_I, mode=wl.mode if mode is None else mode, tau_g=wl.tau_g,
                    seed=wl.seed if seed is None else seed, stream=stream, pop_id_base=pop_index,
                    er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=target,
-                   directions=directions, want_agents=want_agents, want_stage=want_stage)
+                   directions=directions, want_agents=want_agents, want_stage=want_stage, iota=iota)
     return run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K,
                R=wl.R[set_index] if R is None else R, S=wl.S[set_index], m=wl.m[set_index], i0=wl.i0[set_index],
                Z=wl.Z, T=wl.T, tau_E=wl.tau_E, tau_I=wl.tau_I, mode=wl.mode if mode is None else mode,
                tau_g=wl.tau_g, seed=wl.seed if seed is None else seed, stream=stream,
                er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=target, directions=directions,
-               want_agents=want_agents, want_stage=want_stage)
+               want_agents=want_agents, want_stage=want_stage, iota=iota)

@@ -307,19 +307,25 @@ def _soft_setup():
     return wl, tgt
 
 
-def _loss(wl, tgt, R, S, m, i0, mode):
+def _loss(wl, tgt, R, S, m, i0, mode, iota=None):
     return O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=R, S=S,
                  m=m, i0=i0, Z=wl.Z, mode=mode, tau_g=wl.tau_g, er_mean_deg=wl.er_mean_deg,
-                 er_weight=wl.er_weight, target=tgt)["loss"]
+                 er_weight=wl.er_weight, target=tgt, iota=iota)["loss"]
 
 
-def test_soft_tangents_match_finite_differences():
+# an infectiousness profile over the 8 days after exposure (rising, then
+# falling), values exact in float32
+PROFILE = np.array([0.25, 0.5, 0.75, 1.5, 1.75, 1.25, 0.75, 0.25], np.float32)
+
+
+@pytest.mark.parametrize("iota", [None, PROFILE], ids=["flat", "profile"])
+def test_soft_tangents_match_finite_differences(iota):
     wl, tgt = _soft_setup()
     R0, S0, m0, i00 = np.float32(2.5), wl.S[0].copy(), np.float32(0.01), np.float32(0.01)
     dirs = O.standard_directions(wl.K, 8)
-    r = O.run_workload(wl, mode=O.SOFT, R=np.full(wl.K, R0, np.float32), target=tgt, directions=dirs)
+    r = O.run_workload(wl, mode=O.SOFT, R=np.full(wl.K, R0, np.float32), target=tgt, directions=dirs, iota=iota)
     g = r["dL"]
-    assert r["loss"] == pytest.approx(_loss(wl, tgt, R0, S0, m0, i00, O.SOFT), rel=0, abs=0)
+    assert r["loss"] == pytest.approx(_loss(wl, tgt, R0, S0, m0, i00, O.SOFT, iota), rel=0, abs=0)
 
     def fd(k, h):
         def at(delta):
@@ -332,7 +338,7 @@ def test_soft_tangents_match_finite_differences():
                 m = np.float32(m0 + delta)
             else:
                 i0 = np.float32(i00 + delta)
-            return _loss(wl, tgt, R, S, m, i0, O.SOFT)
+            return _loss(wl, tgt, R, S, m, i0, O.SOFT, iota)
         d1 = (at(h) - at(-h)) / (2 * h)
         d2 = (at(h / 2) - at(-h / 2)) / h
         return (4 * d2 - d1) / 3  # Richardson
@@ -387,3 +393,47 @@ def test_two_agent_straight_through_gradient_by_hand():
     assert r["dL"][9] == pytest.approx(dL_dm, rel=1e-12)
     for a in (0, 1, 2, 3, 4, 6, 7):
         assert r["dL"][1 + a] == 0.0
+
+
+def test_profile_of_ones_is_the_flat_model():
+    """A profile of ones reproduces the model without a profile exactly:
+    trajectories, rates and tangents, hard and relaxed."""
+    wl = make_workload("c2", n_agents=2000, K=20)
+    tgt = np.linspace(0.0, 0.3, wl.K)
+    dirs = O.standard_directions(wl.K, 8)
+    for mode in (O.HARD_ST, O.SOFT):
+        a = O.run_workload(wl, mode=mode, target=tgt, directions=dirs, want_agents=True)
+        b = O.run_workload(wl, mode=mode, target=tgt, directions=dirs, want_agents=True,
+                           iota=np.ones(wl.tau_E + wl.tau_I, np.float32))
+        for k in ("counts", "A", "lam", "dL"):
+            assert np.array_equal(a[k], b[k]), (mode, k)
+
+
+def test_profile_indexing_closed_form():
+    """Three agents on a path 0 - 1 - 2, agent 0 initially infected, presymptomatic
+    transmissibility T[E] = 0.5: with R huge on day 0 and zero afterwards,
+    agent 1 is exposed on day 0 and nobody else ever is.  Then agent 2's
+    contact sum on day t is T[stage] * iota[t - 1] (exposed on day 0, days
+    since exposure t), and agent 1's is T[I] * iota[t + tau_E] (an initial
+    infection counts as exposed on day -tau_E - 1)."""
+    tE, tI, K = 3, 5, 12
+    W = tE + tI
+    T = (0.0, 0.5, 1.0, 0.0, 0.0)
+    R = np.zeros(K, np.float32)
+    R[0] = 1e6
+    kw = dict(age=np.zeros(3, np.uint8), pop_offsets=[0, 3], src=[0, 1, 1, 2], dst=[1, 0, 2, 1],
+              w=np.ones(4, np.float32), K=K, R=R, S=[1.0], m=0.0, i0=0.5, Z=[1.0], T=T, tau_E=tE, tau_I=tI,
+              mode=O.PLAIN, iota=PROFILE, want_agents=True, want_stage=True)
+    for seed in range(500):  # a seed whose initial draws infect agent 0 only
+        r = O.run(seed=seed, **kw)
+        if list(r["stage"][0]) == [O.STAGES.index("I"), 0, 0]:
+            break
+    else:
+        pytest.fail("no seed infects agent 0 alone")
+    assert r["h"][0][1] == 1 and r["h"][1:, 1].sum() == 0 and r["h"][:, 2].sum() == 0
+    for t in range(K):
+        a1 = T[2] * PROFILE[t + tE] if t < tI else 0.0
+        k = t  # agent 1's days since exposure
+        a2 = (T[1] if k <= tE else T[2]) * PROFILE[k - 1] if 1 <= k <= W else 0.0
+        assert r["A"][t][1] == np.float64(a1), t
+        assert r["A"][t][2] == np.float64(a2), t
