@@ -153,6 +153,13 @@ typedef struct {
   const float *Z;      /* device [n_pops] rate normaliser > 0 */
   float T[5];          /* host: transmissibility of stages S,E,I,R,M; only E, I may be non-zero */
   float tau_g;         /* Gumbel-softmax temperature in (0,1); used by HARD_ST and SOFT */
+  const float *iota;   /* device [tau_E + tau_I] infectiousness profile over days since exposure
+                          (Section 3.1: the per-contact rate depends on the source's time since
+                          exposure), finite and >= 0, or NULL for a flat profile: an agent exposed
+                          on day u contributes T[stage] * iota[t - u - 1] on day t; an initial
+                          infection counts as exposed on day -tau_E - 1.  B = 1 only (batched runs:
+                          GABM_EUNSUPPORTED); a simulation keeps the choice (profile or not) it was
+                          created with. */
 } gabm_params;
 
 typedef struct {

@@ -49,6 +49,7 @@ gabm_status check_params(const Graph& G, const gabm_params* p, DParams* out) {
   P.TE = p->T[1]; P.TI = p->T[2]; P.tau = p->tau_g;
   P.K = p->K; P.tau_E = p->tau_E; P.tau_I = p->tau_I; P.n_age = G.n_age; P.mode = p->mode;
   P.per_pop = p->per_pop_params ? 1 : 0; P.n_sets = p->n_sets;
+  P.iota = p->iota;
   return GABM_OK;
 }
 
@@ -58,12 +59,19 @@ struct StepInf {
   const void* v;
   int fmt;
   double TE, TI;
+  // records only: the infectiousness profile (null = flat) and the day
+  const float* iota = nullptr;
+  int day = 0, tau_E = 0, W = 0;
   __device__ __forceinline__ double at(int c) const {
     if (fmt == GABM_INF_F32) return (double)((const float*)v)[c];
     if (fmt == GABM_INF_F64) return ((const double*)v)[c];
     if (fmt == GABM_INF_BIT1) return ((((const unsigned long long*)v)[c >> 6] >> (c & 63)) & 1ull) ? TI : 0.0;
-    const uint32_t st = rec_stage(((const uint32_t*)v)[c]);
-    return st == ST_I ? TI : (st == ST_E ? TE : 0.0);
+    const uint32_t r = ((const uint32_t*)v)[c];
+    const uint32_t st = rec_stage(r);
+    const double T = st == ST_I ? TI : (st == ST_E ? TE : 0.0);
+    if (!iota || T == 0.0) return T;
+    const int k = days_since_exposure(r, day, tau_E);
+    return T * (double)iota[(k < 1 ? 1 : (k > W ? W : k)) - 1];
   }
 };
 
@@ -290,6 +298,10 @@ gabm_status gabm_transmit_fwd(gabm_graph g, const void* inf, int32_t fmt, const 
   GABM_CHECK(set >= 0 && set < p->n_sets, GABM_ERANGE, "set outside [0, n_sets)");
   hipStream_t st = (hipStream_t)stream;
   StepInf si{inf, fmt, P.TE, P.TI};
+  si.iota = P.iota;
+  si.day = day;
+  si.tau_E = P.tau_E;
+  si.W = P.tau_E + P.tau_I;
   const DGraph dg = G.view();
   hipLaunchKernelGGL(k_step_gather, dim3(G.n_tiles), dim3(kBlock), 0, st, dg, si, A);
   if (dg.er_total > 0)
@@ -393,6 +405,7 @@ static gabm_status check_run(const Graph& G, const gabm_params* p, const gabm_ru
   GABM_CHECK(run->schedule == 0 || run->schedule == 1, GABM_EINVAL, "schedule must be 0 or 1");
   const int64_t B = p->per_pop_params ? run->n_reps : (int64_t)p->n_sets * run->n_reps;
   if (B > 1) {
+    GABM_CHECK(p->iota == nullptr, GABM_EUNSUPPORTED, "batched runs take no infectiousness profile");
     GABM_CHECK(B <= kBMaxB, GABM_EUNSUPPORTED, "a batched run takes at most 256 simulations");
     GABM_CHECK(!p->per_pop_params, GABM_EUNSUPPORTED,
                "batched runs take one parameter set per simulation (per-population parameters need B = 1)");
@@ -443,7 +456,7 @@ static gabm_status sim_params(gabm_sim s, const gabm_params* p, DParams* P) {
   if (rc != GABM_OK) return rc;
   const Sim& S = s->s;
   GABM_CHECK(p->n_sets == S.n_sets && p->K == S.K && p->tau_E == S.tau_E && p->tau_I == S.tau_I &&
-                 p->mode == S.mode && (p->per_pop_params ? 1 : 0) == S.per_pop,
+                 p->mode == S.mode && (p->per_pop_params ? 1 : 0) == S.per_pop && (p->iota != nullptr) == S.has_iota,
              GABM_EINVAL, "params layout differs from the one the simulation was created with");
   return GABM_OK;
 }

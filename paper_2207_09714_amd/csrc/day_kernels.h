@@ -31,6 +31,11 @@ struct ErArgs {
   int t;
   double TE, TI;
   double* acc;  // [N]
+  // hard forward with an infectiousness profile: the day's records and the
+  // profile (null otherwise)
+  const uint32_t* rec = nullptr;
+  const float* iota = nullptr;
+  int tau_E = 0, W = 0;
 };
 
 template <typename RT>

@@ -59,7 +59,7 @@ __global__ void __launch_bounds__(kBlock) k_init(InitArgs<RT> a) {
       relaxed_init(i0, u, a.P.tau, y0, dy0);
       a.x0[i] = (RT)y0;
       a.Sv[i] = (RT)(1.0 - y0);
-      a.inf[i] = (RT)(a.P.TI * y0);
+      a.inf[i] = (RT)(a.P.TI * iota_at(a.P, a.P.tau_E + 1) * y0);  // day 0: tau_E + 1 days since exposure
       cs = 1.0 - y0;
       ci = y0;
     } else {
@@ -127,6 +127,12 @@ __device__ __forceinline__ void er_pair(const DGraph& G, Rng rng, uint32_t strea
   gj = off + (int)(jp + (jp >= i ? 1u : 0u));
 }
 
+// profile weight of an infectious endpoint from its record
+__device__ __forceinline__ double er_iota(const ErArgs& a, int i) {
+  const int k = days_since_exposure(a.rec[i], a.t, a.tau_E);
+  return (double)a.iota[(k < 1 ? 1 : (k > a.W ? a.W : k)) - 1];
+}
+
 __global__ void k_er_fwd_hard(ErArgs a, const uint32_t* mI, const uint32_t* mE) {
   const double w = a.G.er_w;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < a.G.er_total; k += (int64_t)gridDim.x * blockDim.x) {
@@ -136,6 +142,10 @@ __global__ void k_er_fwd_hard(ErArgs a, const uint32_t* mI, const uint32_t* mE) 
     if (mE) {
       vi += a.TE * (double)mask_bit(mE, i);
       vj += a.TE * (double)mask_bit(mE, j);
+    }
+    if (a.iota) {
+      if (vi != 0.0) vi *= er_iota(a, i);
+      if (vj != 0.0) vj *= er_iota(a, j);
     }
     if (vj != 0.0) atomicAdd(&a.acc[i], w * vj);
     if (vi != 0.0) atomicAdd(&a.acc[j], w * vi);
@@ -216,6 +226,7 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
     if (SOFT) return w * (double)a.inf_cur[c];
     double v = P.TI * (double)mask_bit(a.mI_cur, c);
     if (a.mE_cur) v += P.TE * (double)mask_bit(a.mE_cur, c);
+    if (P.iota && v != 0.0) v *= iota_at(P, days_since_exposure(a.rec_in[c], t, P.tau_E));
     return w * v;
   };
 
@@ -250,17 +261,27 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
         RT* slotp = a.ring + (int64_t)(t % W) * G.N;
         const double old = (double)slotp[i];  // exposure of day t-W
         slotp[i] = (RT)xi;
-        // exposure windows of day t+1
-        double wE = 0.0, wI = 0.0;
+        // exposure windows of day t+1 (wE, wI), and the same weighted by the
+        // infectiousness profile (pE, pI)
+        double wE = 0.0, wI = 0.0, pE = 0.0, pI = 0.0;
         for (int k = 1; k <= W; ++k) {
           const int u_ = t + 1 - k;
           if (u_ < 0) break;
           const double xv = (double)a.ring[(int64_t)(u_ % W) * G.N + i];
-          if (k <= P.tau_E) wE += xv; else wI += xv;
+          if (k <= P.tau_E) {
+            wE += xv;
+            pE += iota_at(P, k) * xv;
+          } else {
+            wI += xv;
+            pI += iota_at(P, k) * xv;
+          }
         }
         const double x0 = (double)a.x0[i];
-        if (t + 1 < P.tau_I) wI += x0;
-        a.inf_next[i] = (RT)(P.TE * wE + P.TI * wI);
+        if (t + 1 < P.tau_I) {
+          wI += x0;
+          pI += iota_at(P, t + 1 + P.tau_E + 1) * x0;
+        }
+        a.inf_next[i] = (RT)(P.TE * pE + P.TI * pI);
         cS = S1; cE = wE; cI = wI; cRM = 1.0 - S1 - wE - wI;
         cD = old + (t == P.tau_I - 1 ? x0 : 0.0);
       } else {
@@ -383,9 +404,10 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
       const double m = P.m[set];
       if (t >= 1) {
         const int d = t - 1;
+        // inf_bar over the days after exposure on day d, weighted by the profile
         double sE = 0.0, sI = 0.0;
         for (int k = 1; k <= W; ++k) {
-          const double v = (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+          const double v = iota_at(P, k) * (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
           if (k <= P.tau_E) sE += v; else sI += v;
         }
         const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + W] : 0.0;
@@ -416,8 +438,8 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
         }
       } else {
         // initial infections: x0_bar = T_I sum_{t<tau_I} inf_bar^t + m Dbar^{tau_I-1} - Sbar^0
-        double sI = 0.0;
-        for (int k = 0; k < P.tau_I; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
+        double sI = 0.0;  // day k is tau_E + 1 + k days after the initial infection's exposure
+        for (int k = 0; k < P.tau_I; ++k) sI += iota_at(P, P.tau_E + 1 + k) * (double)a.ring[(int64_t)(k % W) * G.N + i];
         const double x0_bar =
             P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + P.tau_I - 1] : 0.0) - pre_Sbar;
         const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, a.stream).x);

@@ -172,7 +172,23 @@ struct DParams {
   const float* Z;   // [n_pops]
   double TE, TI, tau;
   int32_t K, tau_E, tau_I, n_age, mode, per_pop, n_sets;
+  const float* iota;  // [tau_E + tau_I] infectiousness over days since exposure, or null (flat)
 };
+
+// Weight of the k-th day after exposure (k = 1 .. tau_E + tau_I): the
+// profile value, 1 when flat.
+__device__ __forceinline__ double iota_at(const DParams& P, int k) {
+  if (!P.iota) return 1.0;
+  const int W = P.tau_E + P.tau_I;
+  return (double)P.iota[(k < 1 ? 1 : (k > W ? W : k)) - 1];
+}
+// Days since exposure on day t of an agent with packed record r (exposure day
+// in the high half); an initial infection (exposure day -1 in the record)
+// counts as exposed on day -tau_E - 1.
+__device__ __forceinline__ int days_since_exposure(uint32_t r, int t, int tau_E) {
+  const int e = (int)(int16_t)(r >> 16);
+  return e < 0 ? t + tau_E + 1 : t - e;
+}
 
 // lambda = R * S[a] * A / Z evaluated left to right in double precision
 __device__ __forceinline__ double rate(double R, double S, double A, double Z) { return R * S * A / Z; }

@@ -167,7 +167,8 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 0;
     s.n_cu = ncu;
   }
-  const bool fast_shape = s.schedule == 0 && s.n_cu > 0 && s.B == 1 && G.n_slices > 0 &&
+  s.has_iota = p->iota != nullptr;
+  const bool fast_shape = s.schedule == 0 && !s.has_iota && s.n_cu > 0 && s.B == 1 && G.n_slices > 0 &&
                           run->precision == GABM_F32 && s.mode != GABM_SOFT;
   s.fast_fwd_ok = fast_shape;
   s.fast_bwd_ok = fast_shape && s.mode == GABM_HARD_ST;
@@ -384,6 +385,12 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   if (has_er) {
     ErArgs e;
     e.G = dg; e.rng = rng; e.stream = stream; e.t = t; e.TE = P.TE; e.TI = P.TI; e.acc = s.A_er;
+    if (P.iota && !soft) {  // hard senders' weights come from their exposure days
+      e.rec = s.rec[s.cur];
+      e.iota = P.iota;
+      e.tau_E = P.tau_E;
+      e.W = P.tau_E + P.tau_I;
+    }
     const int nb = blocks_capped(dg.er_total);
     KTime ke(s, st, GABM_KT_ER);
     if (soft) hipLaunchKernelGGL(k_er_vec<RT>, dim3(nb), dim3(kBlock), 0, st, e, (const RT*)s.inf[s.cur]);
@@ -722,14 +729,14 @@ static void run_backward(Sim& s, const DParams& P, Rng rng, uint32_t stream, con
 // captured or direct execution of a run function
 template <class F>
 static gabm_status execute(Sim& s, bool fwd, const void* k1, const void* k2, const void* k3, const void* k4,
-                           const void* k5, const void* k6, hipStream_t st, F f) {
+                           const void* k5, const void* k6, const void* k7, hipStream_t st, F f) {
   if (!s.use_graph) {
     f(st);
     GABM_HIP(hipGetLastError());
     return GABM_OK;
   }
   auto& cache = fwd ? s.fwd_graphs : s.bwd_graphs;
-  auto key = std::make_tuple(k1, k2, k3, k4, k5, k6);
+  auto key = std::make_tuple(k1, k2, k3, k4, k5, k6, k7);
   auto it = cache.find(key);
   if (it == cache.end()) {
     hipStream_t cs = st;
@@ -770,12 +777,12 @@ gabm_status sim_forward(Sim& s, const DParams& P, const gabm_rng* r, const doubl
   if (s.precision == GABM_F64)
     rc = execute(s, true, P.R, P.S, target, out ? out->counts : nullptr, out ? out->loss : nullptr,
                  (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
                  [&](hipStream_t cs) { run_forward<double>(s, P, rng, stream, target, stride, out, cs); });
   else
     rc = execute(s, true, P.R, P.S, target, out ? out->counts : nullptr, out ? out->loss : nullptr,
                  (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
                  [&](hipStream_t cs) { run_forward<float>(s, P, rng, stream, target, stride, out, cs); });
   if (rc == GABM_OK) {
     s.fwd_done = true;
@@ -797,11 +804,11 @@ gabm_status sim_backward(Sim& s, const DParams& P, const gabm_rng* r, const doub
   if (s.precision == GABM_F64)
     return execute(s, false, P.R, lw, db, out->dR, out->di0,
                    (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
                    [&](hipStream_t cs) { run_backward<double>(s, P, rng, stream, lw, db, out, cs); });
   return execute(s, false, P.R, lw, db, out->dR, out->di0,
                  (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
                  [&](hipStream_t cs) { run_backward<float>(s, P, rng, stream, lw, db, out, cs); });
 }
 

@@ -16,6 +16,7 @@ struct Sim {
   int32_t n_seg = 1;
   int32_t precision = GABM_F32;
   int32_t use_graph = 0;
+  bool has_iota = false;  // created with an infectiousness profile (tile kernels only)
   size_t rsz = 4;        // bytes of one stored real
   int64_t NB = 0;        // N * B
   int64_t NV = 0;        // entries of one per-simulation vector: N * B, or N * 64 * SPL lane-interleaved (B > 32)
@@ -89,7 +90,8 @@ struct Sim {
   bool fwd_done = false;
 
   // captured graphs, keyed by the call's pointers
-  std::map<std::tuple<const void*, const void*, const void*, const void*, const void*, const void*>, hipGraphExec_t>
+  std::map<std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, const void*>,
+           hipGraphExec_t>
       fwd_graphs, bwd_graphs;
 
   void release();
