@@ -368,6 +368,37 @@ def calibration_leg(gabm, torch, wl, g, sched, steps: int = 5):
             "R_blocks": [round(float(x), 4) for x in res.R_blocks[0].cpu()]}
 
 
+# infectiousness over the 8 days after exposure (3 exposed + 5 infectious),
+# values exact in float32; with presymptomatic transmission T[E] = 0.5
+PROFILE = (0.25, 0.5, 0.75, 1.5, 1.75, 1.25, 0.75, 0.25)
+T_PRESYMPTOMATIC = (0.0, 0.5, 1.0, 0.0, 0.0)
+
+
+def profile_leg(gabm, torch, wl, g, E, steps: int = 2, warmup: int = 1):
+    """The headline workload with an infectiousness profile over days since
+    exposure and presymptomatic transmission: differentiable forward+backward
+    with the same checkpoints.  The gathered value is then a per-sender
+    weight, not a bit, so the run uses the receiver-tile kernels."""
+    tgt = load_target(wl.name, wl.K)
+    t = None if tgt is None else torch.tensor(tgt, device="cuda")
+    sim = gabm.Simulator(g, K=wl.K, Z=wl.Z, mode=gabm.HARD_ST, ckpt_every=wl.ckpt_every, tau_g=wl.tau_g,
+                         T=T_PRESYMPTOMATIC, iota=PROFILE)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    for _ in range(warmup):
+        sim.forward(pb, seed=wl.seed, target=t)
+        sim.backward(pb, seed=wl.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.forward(pb, seed=wl.seed, target=t)
+        sim.backward(pb, seed=wl.seed)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": f"{wl.name} with an infectiousness profile over days since exposure and T[E] = 0.5",
+            "profile": list(PROFILE), "T": list(T_PRESYMPTOMATIC), "ms_per_step": dt * 1e3,
+            "value": float(E) * wl.K / dt, "unit": "edge-days/s", "kernels": "receiver-tile kernels"}
+
+
 def cpu_baseline_table():
     """The cpu_baseline leg over every workload: the oracle timed on this host, single thread: C1, C2, C3 and the packed
     populations (C4b, population by population) in full, and 4 of the 128
@@ -589,6 +620,8 @@ def main():
         if res["calibration"]:
             note(f"calibration: {res['calibration']['ms_per_update']:.1f} ms per update, loss "
                  f"{res['calibration']['loss_first']:.4g} -> {res['calibration']['loss_last']:.4g}")
+        res["profile"] = profile_leg(gabm, torch, wl, g, E)
+        note(f"profile leg: {res['profile']['ms_per_step']:.1f} ms per step")
         res["c1"] = c1_leg(gabm, torch, args.steps, args.warmup)
         note(f"c1 plain forward (f64): {res['c1']['graph']['ms_per_run']:.3f} ms per run with hipGraphs")
 
@@ -674,6 +707,8 @@ def main():
         out["c1_plain_f64"] = res["c1"]
     if res.get("calibration"):
         out["calibration"] = res["calibration"]
+    if "profile" in res:
+        out["infectiousness_profile"] = res["profile"]
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
                             "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
     print(json.dumps(out), flush=True)
