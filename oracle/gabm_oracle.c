@@ -148,6 +148,17 @@ static void contact_sum(const ora_cfg *c, const ws_t *ws, int32_t t, const doubl
   int32_t n = c->n_agents;
   for (int32_t i = 0; i < n; ++i) A[i] = 0.0;
   for (int64_t e = 0; e < c->n_edges; ++e) A[c->dst[e]] += (double)c->w[e] * v[c->src[e]];
+  if (c->n_visits > 0) {
+    /* the two-hop sum over locations, without the visitor itself */
+    double *P = c->loc_p;
+    for (int32_t l = 0; l < c->n_locations; ++l) P[l] = 0.0;
+    for (int64_t k = 0; k < c->n_visits; ++k) P[c->visit_loc[k]] += (double)c->visit_w[k] * v[c->visit_agent[k]];
+    for (int64_t k = 0; k < c->n_visits; ++k) {
+      const double wv = (double)c->visit_w[k];
+      const int32_t a = c->visit_agent[k];
+      A[a] += wv * (P[c->visit_loc[k]] - wv * v[a]);
+    }
+  }
   if (c->er_mean_deg > 0.0) {
     double wer = (double)c->er_weight;
     for (int32_t p = 0; p < c->n_pops; ++p) {

@@ -62,6 +62,16 @@ typedef struct {
   const float *iota;          /* [tau_E + tau_I] infectiousness profile over days since exposure, or NULL
                                  (flat): an agent exposed on day u contributes T[stage] * iota[t - u - 1]
                                  on day t; an initial infection counts as exposed on day -tau_E - 1 */
+  /* agent-location layer (the GradABM-JUNE form, Section 6): agent a_v visits location l_v
+   * with weight w_v; a location's pressure is P_l = sum of w_v * v_{a_v} over
+   * its visits, and each visit adds w_v * (P_l - w_v * v_{a_v}) to its agent
+   * (every other visitor, not the agent itself).  Each (agent, location) pair
+   * at most once.  n_visits = 0: none. */
+  int32_t n_locations;
+  int64_t n_visits;
+  const int32_t *visit_agent, *visit_loc;
+  const float *visit_w;
+  double *loc_p;              /* [n_locations] scratch, or NULL when n_visits = 0 */
 } ora_cfg;
 
 typedef struct {

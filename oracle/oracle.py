@@ -40,6 +40,8 @@ class _Cfg(C.Structure):
         ("seed", C.c_uint64), ("stream", C.c_uint32), ("target", C.c_void_p),
         ("ndir", C.c_int32), ("dR", C.c_void_p), ("dS", C.c_void_p), ("dm", C.c_void_p), ("di0", C.c_void_p),
         ("iota", C.c_void_p),
+        ("n_locations", C.c_int32), ("n_visits", C.c_int64), ("visit_agent", C.c_void_p), ("visit_loc", C.c_void_p),
+        ("visit_w", C.c_void_p), ("loc_p", C.c_void_p),
     ]
 
 
@@ -107,12 +109,16 @@ def standard_directions(K: int, n_age: int):
 
 def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), tau_E=3, tau_I=5,
         mode=PLAIN, tau_g=0.5, seed=0, stream=0, pop_id_base=0, er_mean_deg=0.0, er_weight=0.0,
-        target=None, directions=None, want_agents=False, want_stage=False, iota=None):
+        target=None, directions=None, want_agents=False, want_stage=False, iota=None, visits=None):
     """Run one simulation.  Parameters are float32 values (widened exactly).
 
     ``iota`` = infectiousness profile over days since exposure ([tau_E +
     tau_I], float32; None = flat): an agent exposed on day u contributes
     T[stage] * iota[t - u - 1] on day t.
+
+    ``visits`` = (agent[V], location[V], weight[V]) of the agent-location
+    layer, or None: a location's pressure is the weighted sum over its
+    visitors, and each visit adds weight * (pressure - own share) to its agent.
 
     ``directions`` = (dR[nd,K], dS[nd,n_age], dm[nd], di0[nd]) or None.
     Returns a dict with counts [K+1,5], drm [K], deaths [K], loss, and when
@@ -145,6 +151,15 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
             raise ValueError("iota needs tau_E + tau_I values")
         cfg.iota = _p(iv)
         keep.append(iv)
+    if visits is not None:
+        va = np.ascontiguousarray(visits[0], np.int32)
+        vl = np.ascontiguousarray(visits[1], np.int32)
+        vw = np.ascontiguousarray(visits[2], np.float32)
+        nl = int(vl.max()) + 1 if len(vl) else 0
+        lp = np.zeros(max(nl, 1))
+        cfg.n_locations, cfg.n_visits = nl, len(va)
+        cfg.visit_agent, cfg.visit_loc, cfg.visit_w, cfg.loc_p = _p(va), _p(vl), _p(vw), _p(lp)
+        keep += [va, vl, vw, lp]
     nd = 0
     if directions is not None:
         dR, dS, dm, di0 = (np.ascontiguousarray(x, np.float64) for x in directions)
@@ -174,7 +189,7 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
 
 
 def run_workload(wl, *, mode=None, set_index=0, stream=0, seed=None, R=None, target=None, directions=None,
-                 want_agents=False, want_stage=False, pop_index=None, iota=None):
+                 want_agents=False, want_stage=False, pop_index=None, iota=None, visits=None):
     """Run a ``synth`` workload on the oracle (one simulation).  For packed
     populations pass ``pop_index`` to simulate that population alone with its
     own parameter set (populations do not share contacts)."""
@@ -195,4 +210,4 @@ def run_workload(wl, *, mode=None, set_index=0, stream=0, seed=None, R=None, tar
                Z=wl.Z, T=wl.T, tau_E=wl.tau_E, tau_I=wl.tau_I, mode=wl.mode if mode is None else mode,
                tau_g=wl.tau_g, seed=wl.seed if seed is None else seed, stream=stream,
                er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=target, directions=directions,
-               want_agents=want_agents, want_stage=want_stage, iota=iota)
+               want_agents=want_agents, want_stage=want_stage, iota=iota, visits=visits)

@@ -437,3 +437,81 @@ def test_profile_indexing_closed_form():
         a2 = (T[1] if k <= tE else T[2]) * PROFILE[k - 1] if 1 <= k <= W else 0.0
         assert r["A"][t][1] == np.float64(a1), t
         assert r["A"][t][2] == np.float64(a2), t
+
+
+def _random_visits(n, n_loc, rng, max_visits=3):
+    """Each agent visits 1..max_visits distinct locations, weights k/64."""
+    ag, lo, wt = [], [], []
+    for a in range(n):
+        for l in rng.choice(n_loc, rng.integers(1, max_visits + 1), replace=False):
+            ag.append(a)
+            lo.append(int(l))
+            wt.append(rng.integers(1, 65) / 64.0)
+    return np.array(ag, np.int32), np.array(lo, np.int32), np.array(wt, np.float32)
+
+
+def _expanded(n, visits):
+    """The contact graph the location layer stands for: w_ij = sum over shared
+    locations of w_il * w_jl, for i != j, both directions listed."""
+    ag, lo, wt = visits
+    by_loc = {}
+    for a, l, w in zip(ag, lo, wt):
+        by_loc.setdefault(int(l), []).append((int(a), float(w)))
+    pair = {}
+    for members in by_loc.values():
+        for a, wa in members:
+            for b, wb in members:
+                if a != b:
+                    pair[(a, b)] = pair.get((a, b), 0.0) + wa * wb
+    src = np.array([b for (a, b) in pair], np.int32)
+    dst = np.array([a for (a, b) in pair], np.int32)
+    w = np.array([pair[k] for k in pair], np.float32)
+    assert np.array_equal(w.astype(np.float64), np.array([pair[k] for k in pair]))  # exact in float32
+    return src, dst, w
+
+
+@pytest.mark.parametrize("mode", [O.PLAIN, O.HARD_ST, O.SOFT], ids=["plain", "hard_st", "soft"])
+def test_location_layer_equals_its_contact_graph(mode):
+    """The two-hop sum over locations equals the neighbour sum over the
+    expanded graph (w_ij = sum of w_il w_jl over shared locations, i != j):
+    with visit weights k/64 every hard sum is exact, so trajectories, contact
+    sums and loss agree bit for bit; tangents and relaxed values to rounding."""
+    rng = np.random.default_rng(11)
+    n, K = 400, 16
+    visits = _random_visits(n, 40, rng)
+    src, dst, w = _expanded(n, visits)
+    age = (np.arange(n) % 8).astype(np.uint8)
+    S = np.linspace(0.5, 1.0, 8).astype(np.float32)
+    tgt = np.linspace(0.0, 0.5, K)
+    dirs = O.standard_directions(K, 8) if mode != O.PLAIN else None
+    kw = dict(age=age, pop_offsets=[0, n], K=K, R=1.5, S=S, m=0.05, i0=0.05, Z=[40.0], mode=mode, seed=3,
+              target=tgt, directions=dirs, want_agents=True)
+    a = O.run(src=[], dst=[], w=[], visits=visits, **kw)
+    b = O.run(src=src, dst=dst, w=w, **kw)
+    if mode == O.SOFT:
+        assert np.allclose(a["A"], b["A"], rtol=1e-13, atol=1e-15)
+        assert a["loss"] == pytest.approx(b["loss"], rel=1e-12)
+        assert np.allclose(a["dL"], b["dL"], rtol=1e-10, atol=1e-14)
+    else:
+        assert np.array_equal(a["counts"], b["counts"]) and np.array_equal(a["A"], b["A"])
+        assert a["loss"] == b["loss"]
+        if dirs is not None:  # tangents are real-valued: equal up to the order of their sums
+            assert np.allclose(a["dL"], b["dL"], rtol=1e-11, atol=1e-14 * np.abs(b["dL"]).max())
+    assert a["counts"][-1][0] < n  # the layer spreads infection
+
+
+def test_location_layer_excludes_the_visitor():
+    """Agent 0 alone at location 0 and with agent 1 at location 1 (weights
+    1/2 and 3/4 for agent 0, 1/4 for agent 1), agent 1 infected at the start:
+    agent 0's sum is (3/4)(1/4) T_I on every infectious day, agent 1's is 0."""
+    visits = (np.array([0, 0, 1], np.int32), np.array([0, 1, 1], np.int32), np.array([0.5, 0.75, 0.25], np.float32))
+    kw = dict(age=np.zeros(2, np.uint8), pop_offsets=[0, 2], src=[], dst=[], w=[], K=4, R=0.0, S=[1.0], m=0.0,
+              i0=0.5, Z=[1.0], mode=O.PLAIN, visits=visits, want_agents=True, want_stage=True)
+    for seed in range(500):
+        r = O.run(seed=seed, **kw)
+        if list(r["stage"][0]) == [0, O.STAGES.index("I")]:
+            break
+    else:
+        pytest.fail("no seed infects agent 1 alone")
+    for t in range(4):
+        assert r["A"][t][0] == 0.75 * 0.25 and r["A"][t][1] == 0.0
