@@ -98,6 +98,23 @@ typedef struct {
   float er_mean_deg;           /* daily Erdos-Renyi layer per population: round(N_p*mean/2)
                                   undirected pairs drawn each day; 0 = none */
   float er_weight;             /* weight of the daily layer's contacts */
+  /* Agent-location layer (the GradABM-JUNE form, Section 6): visit v puts
+   * agent visit_agent[v] at location visit_loc[v] with weight visit_w[v].
+   * Location l's pressure is P_l = sum of w_v * x_{a_v} over its visits (x =
+   * the visitor's infectiousness: T[stage] times the profile, or the relaxed
+   * value); each visit adds w_v * (P_l - w_v * x_{a_v}) to its agent's
+   * neighbour sum, so the agent meets every other visitor of l with weight
+   * w_v * w_u and never itself.  This equals a static layer with
+   * w_ij = sum over shared locations of w_il * w_jl, stored in O(visits)
+   * instead of O(sum of squared location sizes).  Every visitor of a location
+   * must belong to one population (GABM_ERANGE otherwise); an agent visits a
+   * location at most once (GABM_EINVAL).  n_visits = 0: no such layer. */
+  int32_t n_locations;         /* >= 0; location ids in [0, n_locations) */
+  int32_t reserved1;
+  int64_t n_visits;            /* >= 0 */
+  const int32_t *visit_agent;  /* device [n_visits] */
+  const int32_t *visit_loc;    /* device [n_visits] */
+  const float *visit_w;        /* device [n_visits], finite and >= 0 */
 } gabm_graph_desc;
 
 /* Builds the destination-sorted CSR (rows = receivers, each row sorted by
@@ -124,6 +141,9 @@ typedef struct {
                                (no contacts, or 2^24 agents or more) */
   int32_t reserved0;
   int64_t n_stream_chunks;  /* 256-contact chunks of that stream */
+  int32_t n_locations;      /* agent-location layer: locations and visits (0 = none) */
+  int32_t reserved1;
+  int64_t n_visits;
 } gabm_graph_stats;
 
 gabm_status gabm_graph_info(gabm_graph g, gabm_graph_stats *stats);
@@ -183,7 +203,8 @@ enum { GABM_INF_REC = 0,   /* gabm_rec[N]: T[stage] */
  * w * inf_j, plus the day's random layer (when the graph has one), and
  * lambda_i = R^day * S[a_i] * A_i / Z_p for parameter set `set`.  Sums are
  * formed in double precision.  A, lambda: device double[N] (lambda may be
- * NULL). */
+ * NULL).  A graph with an agent-location layer: GABM_EUNSUPPORTED (that
+ * layer runs in whole runs, gabm_sim_*, only). */
 gabm_status gabm_transmit_fwd(gabm_graph g, const void *inf, int32_t inf_fmt, const gabm_params *p, int32_t set,
                               const gabm_rng *rng, int32_t day, double *A, double *lambda, void *stream);
 
@@ -206,7 +227,8 @@ gabm_status gabm_progress_stages(gabm_graph g, const gabm_rec *rec_in, const uin
 /* Backward of the neighbour sum (adjoint of gabm_transmit_fwd with respect
  * to inf): infbar_j = sum_{i in N(j)} w_ij * g_i, a gather over the same CSR
  * (valid because the contact graph is symmetric), plus the day's random
- * layer.  g, infbar: device double[N]. */
+ * layer.  g, infbar: device double[N].  A graph with an agent-location
+ * layer: GABM_EUNSUPPORTED. */
 gabm_status gabm_transmit_bwd(gabm_graph g, const double *gvec, const gabm_rng *rng, int32_t day, double *infbar,
                               void *stream);
 
@@ -249,7 +271,9 @@ typedef struct {
 /* Creates a simulation object on a built graph for the given parameter
  * layout (n_sets, K, tau_E, tau_I, mode, per_pop_params of `p`; pointers in
  * `p` are not kept).  Allocates its device workspace (gabm_sim_workspace_size
- * bytes) with hipMalloc. */
+ * bytes) with hipMalloc.  A graph with an agent-location layer takes B = 1
+ * (GABM_EUNSUPPORTED for batched runs); the layer adds two launches per day
+ * in each direction (location pressures, then the per-agent sums). */
 gabm_status gabm_sim_create(gabm_graph g, const gabm_params *p, const gabm_run_desc *run, gabm_sim *out);
 gabm_status gabm_sim_workspace_size(gabm_graph g, const gabm_params *p, const gabm_run_desc *run, size_t *bytes);
 
@@ -319,7 +343,8 @@ gabm_status gabm_sim_records(gabm_sim s, const gabm_rec **rec);
  *   GABM_KT_GATHER_BWD  persistent neighbour sum of the reverse step
  *   GABM_KT_AGENT_BWD   per-agent reverse step (window ring, adjoint, grads)
  *   GABM_KT_DAY_BWD     fused tiled reverse step
- *   GABM_KT_ER          daily random layer (forward or reverse)          */
+ *   GABM_KT_ER          daily random layer (forward or reverse)
+ *   GABM_KT_LOC         agent-location layer (pressures and per-agent sums) */
 enum {
   GABM_KT_GATHER_FWD = 0,
   GABM_KT_AGENT_FWD = 1,
@@ -328,7 +353,8 @@ enum {
   GABM_KT_AGENT_BWD = 4,
   GABM_KT_DAY_BWD = 5,
   GABM_KT_ER = 6,
-  GABM_KT_N = 7
+  GABM_KT_LOC = 7,
+  GABM_KT_N = 8
 };
 typedef struct {
   double ms[GABM_KT_N];        /* total duration per class */

@@ -40,14 +40,17 @@ class GabmError(RuntimeError):
 class GraphDesc(C.Structure):
     _fields_ = [("n_agents", C.c_int32), ("n_pops", C.c_int32), ("pop_offsets", C.c_void_p), ("age", C.c_void_p),
                 ("n_age", C.c_int32), ("n_edges", C.c_int64), ("src", C.c_void_p), ("dst", C.c_void_p),
-                ("w", C.c_void_p), ("flags", C.c_uint32), ("er_mean_deg", C.c_float), ("er_weight", C.c_float)]
+                ("w", C.c_void_p), ("flags", C.c_uint32), ("er_mean_deg", C.c_float), ("er_weight", C.c_float),
+                ("n_locations", C.c_int32), ("reserved1", C.c_int32), ("n_visits", C.c_int64),
+                ("visit_agent", C.c_void_p), ("visit_loc", C.c_void_p), ("visit_w", C.c_void_p)]
 
 
 class GraphStats(C.Structure):
     _fields_ = [("n_agents", C.c_int32), ("n_pops", C.c_int32), ("n_age", C.c_int32), ("n_edges", C.c_int64),
                 ("max_degree", C.c_int32), ("n_tiles", C.c_int32), ("n_long_rows", C.c_int32),
                 ("weight_sum", C.c_double), ("er_pairs_per_day", C.c_int64), ("n_sender_slices", C.c_int32),
-                ("reserved0", C.c_int32), ("n_stream_chunks", C.c_int64)]
+                ("reserved0", C.c_int32), ("n_stream_chunks", C.c_int64), ("n_locations", C.c_int32),
+                ("reserved1", C.c_int32), ("n_visits", C.c_int64)]
 
 
 class Params(C.Structure):
@@ -66,7 +69,7 @@ class RunDesc(C.Structure):
                 ("use_hip_graph", C.c_int32), ("schedule", C.c_int32), ("time_kernels", C.c_int32)]
 
 
-KT_CLASSES = ("gather_fwd", "agent_fwd", "day_fwd", "gather_bwd", "agent_bwd", "day_bwd", "er")
+KT_CLASSES = ("gather_fwd", "agent_fwd", "day_fwd", "gather_bwd", "agent_bwd", "day_bwd", "er", "loc")
 
 
 class KernelTimes(C.Structure):

@@ -244,6 +244,10 @@ gabm_status gabm_graph_build(const gabm_graph_desc* d, void* stream, gabm_graph*
   GABM_CHECK(std::isfinite(d->er_mean_deg) && d->er_mean_deg >= 0.f && std::isfinite(d->er_weight) &&
                  d->er_weight >= 0.f,
              GABM_EINVAL, "daily layer mean degree and weight must be finite and >= 0");
+  GABM_CHECK(d->n_locations >= 0 && d->n_visits >= 0, GABM_EINVAL, "n_locations and n_visits must be >= 0");
+  GABM_CHECK(d->n_visits == 0 || (d->visit_agent && d->visit_loc && d->visit_w), GABM_EINVAL,
+             "visit_agent, visit_loc or visit_w is NULL");
+  GABM_CHECK(d->n_visits < ((int64_t)1 << 31), GABM_ERANGE, "too many visits");
   const int64_t E = (d->flags & GABM_SYMMETRIZE) ? 2 * d->n_edges : d->n_edges;
   GABM_CHECK(E < ((int64_t)1 << 40), GABM_ERANGE, "too many contacts");
   gabm_graph h = new (std::nothrow) gabm_graph_s();
@@ -267,6 +271,9 @@ gabm_status gabm_graph_info(gabm_graph g, gabm_graph_stats* s) {
   s->n_sender_slices = G.n_slices;
   s->reserved0 = 0;
   s->n_stream_chunks = G.slice_chunk.empty() ? 0 : G.slice_chunk.back();
+  s->n_locations = G.n_loc;
+  s->reserved1 = 0;
+  s->n_visits = G.n_visits;
   return GABM_OK;
 }
 
@@ -291,6 +298,7 @@ gabm_status gabm_transmit_fwd(gabm_graph g, const void* inf, int32_t fmt, const 
   GABM_CHECK(fmt == GABM_INF_REC || fmt == GABM_INF_F32 || fmt == GABM_INF_F64 || fmt == GABM_INF_BIT1, GABM_EINVAL,
              "unknown inf format");
   const Graph& G = g->g;
+  GABM_CHECK(G.n_visits == 0, GABM_EUNSUPPORTED, "single-step sums do not cover the agent-location layer");
   DParams P;
   gabm_status rc = check_params(G, p, &P);
   if (rc != GABM_OK) return rc;
@@ -349,6 +357,7 @@ gabm_status gabm_transmit_bwd(gabm_graph g, const double* gvec, const gabm_rng* 
   GABM_CHECK(g && gvec && infbar && rng, GABM_EINVAL, "graph, g, infbar or rng is NULL");
   GABM_CHECK(day >= 0, GABM_ERANGE, "day must be >= 0");
   const Graph& G = g->g;
+  GABM_CHECK(G.n_visits == 0, GABM_EUNSUPPORTED, "single-step sums do not cover the agent-location layer");
   hipStream_t st = (hipStream_t)stream;
   StepInf si{gvec, GABM_INF_F64, 0.0, 0.0};
   const DGraph dg = G.view();
@@ -406,6 +415,7 @@ static gabm_status check_run(const Graph& G, const gabm_params* p, const gabm_ru
   const int64_t B = p->per_pop_params ? run->n_reps : (int64_t)p->n_sets * run->n_reps;
   if (B > 1) {
     GABM_CHECK(p->iota == nullptr, GABM_EUNSUPPORTED, "batched runs take no infectiousness profile");
+    GABM_CHECK(G.n_visits == 0, GABM_EUNSUPPORTED, "batched runs take no agent-location layer");
     GABM_CHECK(B <= kBMaxB, GABM_EUNSUPPORTED, "a batched run takes at most 256 simulations");
     GABM_CHECK(!p->per_pop_params, GABM_EUNSUPPORTED,
                "batched runs take one parameter set per simulation (per-population parameters need B = 1)");

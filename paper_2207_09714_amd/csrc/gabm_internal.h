@@ -52,6 +52,20 @@ struct Graph {
   uint16_t* pop_of = nullptr;
   int32_t* pop_off = nullptr;
   int64_t* er_off = nullptr;
+  // agent-location layer: visits sorted by location (stable in input order)
+  // and by agent; n_visits = 0 when the graph has none
+  int32_t n_loc = 0;
+  int64_t n_visits = 0;
+  int32_t* lv_agent = nullptr;  // [V] visitor of each location-sorted visit
+  int32_t* lv_loc = nullptr;    // [V] its location (runs of equal ids)
+  float* lv_w = nullptr;        // [V]
+  int64_t* av_ptr = nullptr;    // [N+1] visits of agent i: av_ptr[i] .. av_ptr[i+1]
+  int32_t* av_loc = nullptr;    // [V]
+  float* av_w = nullptr;        // [V]
+  bool has_er() const { return !er_off_h.empty() && er_off_h.back() > 0; }
+  // a layer whose sums arrive through the per-agent accumulators (daily random
+  // pairs, or locations)
+  bool has_aux() const { return has_er() || n_visits > 0; }
 
   DGraph view() const {
     DGraph g;

@@ -421,6 +421,9 @@ void Graph::release() {
   slice_chunk.clear();
   age = nullptr; pop_of = nullptr;
   pop_off = nullptr; er_off = nullptr;
+  hipFree(lv_agent); hipFree(lv_loc); hipFree(lv_w); hipFree(av_ptr); hipFree(av_loc); hipFree(av_w);
+  lv_agent = nullptr; lv_loc = nullptr; lv_w = nullptr; av_ptr = nullptr; av_loc = nullptr; av_w = nullptr;
+  n_loc = 0; n_visits = 0;
 }
 
 static int grid_for(int64_t n, int per = kBlock) {
@@ -532,6 +535,82 @@ static gabm_status build_sliced_stream(Graph& G, hipStream_t st) {
   return GABM_OK;
 }
 
+// Agent-location layer: validates the visits on the host and stores them
+// twice, grouped by location (the pressure pass reads runs of one location)
+// and by agent (the per-agent pass).  Both groupings are counting sorts,
+// stable in input order.
+static gabm_status build_locations(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
+  const int64_t V = d->n_visits;
+  const int32_t L = d->n_locations, N = d->n_agents;
+  if (V == 0) return GABM_OK;
+  std::vector<int32_t> va(V), vl(V);
+  std::vector<float> vw(V);
+  GABM_HIP(hipMemcpyAsync(va.data(), d->visit_agent, sizeof(int32_t) * V, hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipMemcpyAsync(vl.data(), d->visit_loc, sizeof(int32_t) * V, hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipMemcpyAsync(vw.data(), d->visit_w, sizeof(float) * V, hipMemcpyDeviceToHost, st));
+  GABM_HIP(hipStreamSynchronize(st));
+  std::vector<int32_t> lpop(L, -1);
+  std::vector<int64_t> lcnt(L + 1, 0), acnt((size_t)N + 1, 0);
+  for (int64_t v = 0; v < V; ++v) {
+    const int32_t a = va[v], l = vl[v];
+    GABM_CHECK(a >= 0 && a < N, GABM_ERANGE, "visit with agent id outside [0, n_agents)");
+    GABM_CHECK(l >= 0 && l < L, GABM_ERANGE, "visit with location id outside [0, n_locations)");
+    GABM_CHECK(std::isfinite(vw[v]) && vw[v] >= 0.f, GABM_EINVAL, "visit weight negative or not finite");
+    const int32_t p = (int32_t)(std::upper_bound(G.pop_off_h.begin(), G.pop_off_h.end(), a) - G.pop_off_h.begin()) - 1;
+    GABM_CHECK(lpop[l] < 0 || lpop[l] == p, GABM_ERANGE, "location visited from different populations");
+    lpop[l] = p;
+    ++lcnt[l + 1];
+    ++acnt[(size_t)a + 1];
+  }
+  for (int32_t l = 0; l < L; ++l) lcnt[l + 1] += lcnt[l];
+  for (int32_t i = 0; i < N; ++i) acnt[(size_t)i + 1] += acnt[i];
+  std::vector<int32_t> lv_a(V), lv_l(V), av_l(V);
+  std::vector<float> lv_wh(V), av_wh(V);
+  {
+    std::vector<int64_t> cur(lcnt.begin(), lcnt.end() - 1);
+    for (int64_t v = 0; v < V; ++v) {
+      const int64_t k = cur[vl[v]]++;
+      lv_a[k] = va[v];
+      lv_l[k] = vl[v];
+      lv_wh[k] = vw[v];
+    }
+  }
+  {
+    std::vector<int64_t> cur(acnt.begin(), acnt.end() - 1);
+    for (int64_t v = 0; v < V; ++v) {
+      const int64_t k = cur[va[v]]++;
+      av_l[k] = vl[v];
+      av_wh[k] = vw[v];
+    }
+  }
+  // one visit per (agent, location): a second would make the agent meet itself
+  for (int32_t i = 0; i < N; ++i) {
+    const int64_t b = acnt[i], e = acnt[(size_t)i + 1];
+    if (e - b < 2) continue;
+    std::vector<int32_t> ls(av_l.begin() + b, av_l.begin() + e);
+    std::sort(ls.begin(), ls.end());
+    GABM_CHECK(std::adjacent_find(ls.begin(), ls.end()) == ls.end(), GABM_EINVAL,
+               "an agent visits the same location twice");
+  }
+  G.n_loc = L;
+  G.n_visits = V;
+  GABM_HIP(dalloc(&G.lv_agent, V));
+  GABM_HIP(dalloc(&G.lv_loc, V));
+  GABM_HIP(dalloc(&G.lv_w, V));
+  GABM_HIP(dalloc(&G.av_ptr, (size_t)N + 1));
+  GABM_HIP(dalloc(&G.av_loc, V));
+  GABM_HIP(dalloc(&G.av_w, V));
+  GABM_HIP(hipMemcpyAsync(G.lv_agent, lv_a.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.lv_loc, lv_l.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.lv_w, lv_wh.data(), sizeof(float) * V, hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.av_ptr, acnt.data(), sizeof(int64_t) * ((size_t)N + 1), hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.av_loc, av_l.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
+  GABM_HIP(hipMemcpyAsync(G.av_w, av_wh.data(), sizeof(float) * V, hipMemcpyHostToDevice, st));
+  // the host vectors die on return: wait for the copies
+  GABM_HIP(hipStreamSynchronize(st));
+  return GABM_OK;
+}
+
 gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
   const int32_t N = d->n_agents;
   const int sym = (d->flags & GABM_SYMMETRIZE) ? 1 : 0;
@@ -594,6 +673,13 @@ gabm_status build_graph(const gabm_graph_desc* d, hipStream_t st, Graph& G) {
     if (hflag & BAD_AGE) { set_error("age group >= n_age"); return GABM_ERANGE; }
     set_error("contact weight negative or not finite");
     return GABM_EINVAL;
+  }
+  {
+    const gabm_status rc = build_locations(d, st, G);
+    if (rc != GABM_OK) {
+      cleanup();
+      return rc;
+    }
   }
 
   GABM_HIP(hipMemsetAsync(deg, 0, sizeof(unsigned long long) * n1, st));

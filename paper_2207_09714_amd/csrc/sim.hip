@@ -9,6 +9,7 @@
 
 #include "batched.h"
 #include "day_kernels.h"
+#include "loc.h"
 #include "sim_internal.h"
 
 namespace gabm {
@@ -81,7 +82,7 @@ void Sim::release() {
   bwd_graphs.clear();
   void* ps[] = {rec[0], rec[1], maskI[0], maskI[1], maskI[2], maskE[0], maskE[1], maskE[2], A_er, Sv, x0, xi_ring,
                 inf[0], inf[1], A_st, fl_st, S_st, ck_rec, ck_soft, cnt, cnt0, drm, Dbar, Dbar_eff, ring, Sbar, g[0], g[1],
-                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece, anyI[0], anyI[1], anyI[2], wq};
+                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece, anyI[0], anyI[1], anyI[2], wq, loc_P};
   for (void* p : ps) hipFree(p);
 }
 
@@ -90,22 +91,22 @@ int sim_n_out(const Sim& s) { return s.per_pop ? s.n_reps * s.G->n_pops : s.B; }
 // bytes of every device buffer of a simulation (the same arithmetic as the allocation)
 struct Layout {
   size_t rec, mask, aer, soft_vec, soft_ring, st_A, st_fl, st_S, ck_rec, ck_soft, cnt, cnt0, drm, ring, sbar, g,
-      ier, gR, gS, gi0;
+      ier, gR, gS, gi0, locp;
   size_t total() const {
     return 2 * rec + 6 * mask + aer + 4 * soft_vec + soft_ring + st_A + st_fl + st_S + ck_rec + ck_soft + cnt + cnt0 +
-           3 * drm + ring + sbar + 2 * g + ier + gR + gS + gi0;
+           3 * drm + ring + sbar + 2 * g + ier + gR + gS + gi0 + locp;
   }
 };
 
 static Layout layout(const Graph& G, int B, int64_t NVs, int n_out, int n_sets, int K, int W, int ckpt, int n_seg,
-                     int mode, size_t rsz, bool has_er, int64_t mask_words) {
+                     int mode, size_t rsz, bool has_aux, int64_t mask_words) {
   Layout L{};
   const size_t NB = (size_t)G.N * B;
   const size_t NV = (size_t)NVs;
   const bool soft = mode == GABM_SOFT;
   L.rec = NB * 4;
   L.mask = soft ? 0 : (size_t)mask_words * 8;
-  L.aer = has_er ? NB * 8 : 0;
+  L.aer = has_aux ? NB * 8 : 0;
   L.soft_vec = soft ? NB * rsz : 0;
   L.soft_ring = soft ? (size_t)W * NB * rsz : 0;
   const bool diff = mode != GABM_PLAIN;
@@ -121,7 +122,8 @@ static Layout layout(const Graph& G, int B, int64_t NVs, int n_out, int n_sets, 
   L.ring = diff ? (size_t)W * NV * rsz : 0;
   L.sbar = diff ? NV * rsz : 0;
   L.g = diff ? NV * rsz : 0;
-  L.ier = (diff && has_er) ? NB * 8 : 0;
+  L.ier = (diff && has_aux) ? NB * 8 : 0;
+  L.locp = (size_t)G.n_loc * 8;
   L.gR = (size_t)n_sets * K * kSlots * 8;
   L.gS = (size_t)n_sets * G.n_age * kSlots * 8;
   L.gi0 = (size_t)n_sets * kSlots * 8;
@@ -196,8 +198,8 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
 gabm_status sim_workspace(const Graph& G, const gabm_params* p, const gabm_run_desc* run, size_t* bytes) {
   Sim s;
   sim_shape(s, G, p, run);
-  Layout L = layout(G, s.B, s.NV, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz,
-                    G.er_off_h.back() > 0, s.mask_words);
+  Layout L = layout(G, s.B, s.NV, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz, G.has_aux(),
+                    s.mask_words);
   *bytes = L.total() + extra_bytes(s);
   return GABM_OK;
 }
@@ -236,8 +238,8 @@ static gabm_status batched_setup(Sim& s) {
 
 gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc* run, Sim& s) {
   sim_shape(s, G, p, run);
-  const bool has_er = G.er_off_h.back() > 0;
-  Layout L = layout(G, s.B, s.NV, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz, has_er, s.mask_words);
+  Layout L = layout(G, s.B, s.NV, sim_n_out(s), s.n_sets, s.K, s.W, s.ckpt, s.n_seg, s.mode, s.rsz, G.has_aux(),
+                    s.mask_words);
   auto al = [&](void** ptr, size_t n) -> gabm_status {
     if (n == 0) {
       *ptr = nullptr;
@@ -282,6 +284,7 @@ gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc
   AL(s.g[0], L.g);
   AL(s.g[1], L.g);
   AL(s.infbar_er, L.ier);
+  AL(s.loc_P, L.locp);
   AL(s.gR, L.gR);
   AL(s.gS, L.gS);
   AL(s.gi0, L.gi0);
@@ -350,6 +353,21 @@ static GatherArgs gather_args(const Sim& s, const DGraph& dg, const unsigned lon
   return ga;
 }
 
+// the agent-location layer's two passes for one day, adding into `acc`
+template <class V>
+static void loc_pass(Sim& s, const V& val, double* acc, hipStream_t st) {
+  const Graph& G = *s.G;
+  LocView L;
+  L.N = G.N; L.n_loc = G.n_loc; L.V = G.n_visits;
+  L.lv_agent = G.lv_agent; L.lv_loc = G.lv_loc; L.lv_w = G.lv_w;
+  L.av_ptr = G.av_ptr; L.av_loc = G.av_loc; L.av_w = G.av_w;
+  KTime kt(s, st, GABM_KT_LOC);
+  fill0(s.loc_P, (size_t)G.n_loc * 8, st);
+  hipLaunchKernelGGL(k_loc_pressure<V>, dim3(blocks_capped(G.n_visits)), dim3(kBlock), 0, st, L, val, s.loc_P);
+  hipLaunchKernelGGL(k_loc_gather<V>, dim3(blocks_capped(G.N)), dim3(kBlock), 0, st, L, val, (const double*)s.loc_P,
+                     acc);
+}
+
 template <typename RT>
 static void b1_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStream_t st) {
   const Graph& G = *s.G;
@@ -380,7 +398,7 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   const Graph& G = *s.G;
   const bool soft = s.mode == GABM_SOFT;
   const bool withE = P.TE != 0.0;
-  const bool has_er = G.er_off_h.back() > 0;
+  const bool has_er = G.has_er();
   const DGraph dg = G.view();
   if (has_er) {
     ErArgs e;
@@ -397,6 +415,27 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     else hipLaunchKernelGGL(k_er_fwd_hard, dim3(nb), dim3(kBlock), 0, st, e, (const uint32_t*)s.maskI[t % 3],
                             withE ? (const uint32_t*)s.maskE[t % 3] : nullptr);
   }
+  if (G.n_visits > 0) {
+    if (soft) {
+      LocVecVal<RT> v;
+      v.v = (const RT*)s.inf[s.cur];
+      loc_pass(s, v, s.A_er, st);
+    } else {
+      LocHardVal v;
+      v.mI = (const uint32_t*)s.maskI[t % 3];
+      v.mE = withE ? (const uint32_t*)s.maskE[t % 3] : nullptr;
+      v.TI = P.TI;
+      v.TE = P.TE;
+      if (P.iota) {
+        v.rec = s.rec[s.cur];
+        v.iota = P.iota;
+        v.t = t;
+        v.tau_E = P.tau_E;
+        v.W = P.tau_E + P.tau_I;
+      }
+      loc_pass(s, v, s.A_er, st);
+    }
+  }
   FwdArgs<RT> a;
   a.G = dg; a.P = P; a.rng = rng; a.stream = stream; a.t = t;
   a.rec_in = s.rec[s.cur]; a.rec_out = s.rec[1 - s.cur];
@@ -407,7 +446,7 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.mI_clr = s.maskI[(t + 2) % 3];
   a.mE_clr = withE ? s.maskE[(t + 2) % 3] : nullptr;
   a.mask_words = s.mask_words;
-  a.A_er = has_er ? s.A_er : nullptr;
+  a.A_er = G.has_aux() ? s.A_er : nullptr;
   a.inf_cur = (const RT*)s.inf[s.cur];
   a.inf_next = (RT*)s.inf[1 - s.cur];
   a.Sv = (RT*)s.Sv; a.x0 = (const RT*)s.x0; a.ring = (RT*)s.xi_ring;
@@ -490,7 +529,7 @@ template <typename RT>
 static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t, int slot, hipStream_t st) {
   const Graph& G = *s.G;
   const bool soft = s.mode == GABM_SOFT;
-  const bool has_er = G.er_off_h.back() > 0;
+  const bool has_er = G.has_er();
   const DGraph dg = G.view();
   const bool gather = t < s.K;
   if (gather && has_er) {
@@ -499,11 +538,16 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     KTime ke(s, st, GABM_KT_ER);
     hipLaunchKernelGGL(k_er_vec<RT>, dim3(blocks_capped(dg.er_total)), dim3(kBlock), 0, st, e, (const RT*)s.g[t & 1]);
   }
+  if (gather && G.n_visits > 0) {
+    LocVecVal<RT> v;
+    v.v = (const RT*)s.g[t & 1];
+    loc_pass(s, v, s.infbar_er, st);
+  }
   BwdArgs<RT> a;
   a.G = dg; a.P = P; a.rng = rng; a.stream = stream; a.t = t; a.do_gather = gather ? 1 : 0;
   a.g_cur = (const RT*)s.g[t & 1];
   a.g_prev = (RT*)s.g[(t + 1) & 1];
-  a.infbar_er = (gather && has_er) ? s.infbar_er : nullptr;
+  a.infbar_er = (gather && G.has_aux()) ? s.infbar_er : nullptr;
   a.ring = (RT*)s.ring; a.Sbar = (RT*)s.Sbar;
   a.A_st = t >= 1 ? store_ptr<RT>(s.A_st, s, slot) : nullptr;
   a.fl_st = (t >= 1 && !soft) ? s.fl_st + (int64_t)slot * s.NV : nullptr;

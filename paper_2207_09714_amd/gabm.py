@@ -51,7 +51,10 @@ class Graph:
     tensors; they are copied to the device and then into the library."""
 
     def __init__(self, *, n_agents, src, dst, w=None, age, n_age=8, pop_offsets=None, er_mean_deg=0.0,
-                 er_weight=0.0, symmetrize=False, check_symmetric=True, stream=None):
+                 er_weight=0.0, symmetrize=False, check_symmetric=True, visits=None, n_locations=None,
+                 stream=None):
+        """visits: optional agent-location layer (agent[V], location[V],
+        weight[V]); n_locations defaults to the largest location id + 1."""
         dev = _dev()
         self.n_agents = int(n_agents)
         offs = np.asarray([0, self.n_agents] if pop_offsets is None else pop_offsets, np.int32)
@@ -67,6 +70,16 @@ class Graph:
         d.w = None if w_d is None else w_d.data_ptr()
         d.flags = (L.SYMMETRIZE if symmetrize else 0) | (L.CHECK_SYMMETRIC if check_symmetric else 0)
         d.er_mean_deg, d.er_weight = float(er_mean_deg), float(er_weight)
+        if visits is not None:
+            va_d = _on_dev(visits[0], torch.int32, dev)
+            vl_d = _on_dev(visits[1], torch.int32, dev)
+            vw_d = _on_dev(visits[2], torch.float32, dev)
+            if not (va_d.numel() == vl_d.numel() == vw_d.numel()):
+                raise ValueError("visit arrays differ in length")
+            if n_locations is None:
+                n_locations = int(vl_d.max().item()) + 1 if vl_d.numel() else 0
+            d.n_locations, d.n_visits = int(n_locations), int(va_d.numel())
+            d.visit_agent, d.visit_loc, d.visit_w = va_d.data_ptr(), vl_d.data_ptr(), vw_d.data_ptr()
         h = C.c_void_p()
         torch.cuda.synchronize()
         check(lib().gabm_graph_build(C.byref(d), C.c_void_p(_stream(stream)), C.byref(h)))

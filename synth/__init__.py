@@ -15,5 +15,7 @@ from .graphs import (  # noqa: F401
     complete_pairs,
     to_symmetric_coo,
     quantized_unit_weights,
+    location_visits,
+    location_degree,
 )
 from .workloads import Workload, make_workload, CONFIG_NAMES  # noqa: F401

@@ -195,3 +195,53 @@ def to_symmetric_coo(layers, offset: int = 0):
         np.concatenate(dsts).astype(np.int32),
         np.concatenate(ws).astype(np.float32),
     )
+
+
+def location_visits(pop: Population, rng: np.random.Generator, *, school=(100, 400), work=(5, 60),
+                    work_share: float = 0.7, leisure=(10, 80), leisure_share: float = 0.5, kmax: int = 16):
+    """One day of agent-location visits shaped like the JUNE model's venues
+    (the agent-location bipartite graph of the paper's GradABM-JUNE
+    discussion; no census data here, so sizes are drawn):
+
+    * schools: every agent of age groups 0-1, in venues of size uniform on
+      ``school``;
+    * workplaces: a ``work_share`` subset of age groups 2-5, venues of size
+      uniform on ``work``;
+    * leisure: a ``leisure_share`` subset of everyone, venues of size
+      uniform on ``leisure``.
+
+    Venues never span populations; an agent visits at most one venue of each
+    kind, so never one location twice.  Weights are k/64 with k uniform on
+    1..kmax (exact products and sums in float64).  Returns
+    ``(agent int32[V], location int32[V], weight float32[V], n_locations)``.
+    """
+    ag, lo = [], []
+    n_loc = 0
+    for p in range(pop.n_pops):
+        a0, a1 = int(pop.pop_offsets[p]), int(pop.pop_offsets[p + 1])
+        ids = np.arange(a0, a1, dtype=np.int64)
+        age = pop.age[a0:a1]
+        kinds = ((ids[age <= 1], 1.0, school), (ids[(age >= 2) & (age <= 5)], work_share, work),
+                 (ids, leisure_share, leisure))
+        for cand, share, (s_lo, s_hi) in kinds:
+            members = rng.permutation(cand)[: int(round(share * len(cand)))]
+            if len(members) == 0:
+                continue
+            sizes = _split_sizes(len(members), rng, s_lo, s_hi)
+            ag.append(members)
+            lo.append(n_loc + np.repeat(np.arange(len(sizes)), sizes))
+            n_loc += len(sizes)
+    agent = np.concatenate(ag).astype(np.int32) if ag else np.zeros(0, np.int32)
+    loc = np.concatenate(lo).astype(np.int32) if lo else np.zeros(0, np.int32)
+    w = (rng.integers(1, kmax + 1, size=len(agent)) / 64.0).astype(np.float32)
+    return agent, loc, w, n_loc
+
+
+def location_degree(n_agents: int, visits) -> np.ndarray:
+    """Per-agent weighted degree the visits stand for: for agent i, the sum
+    over its locations l of w_il times the other visitors' weights at l
+    (the contact weight of i with j being the sum of w_il * w_jl)."""
+    agent, loc, w = visits[0], visits[1], np.asarray(visits[2], np.float64)
+    n_loc = int(loc.max()) + 1 if len(loc) else 0
+    tot = np.bincount(loc, weights=w, minlength=n_loc)
+    return np.bincount(agent, weights=w * (tot[loc] - w), minlength=n_agents)
