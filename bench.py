@@ -399,6 +399,62 @@ def profile_leg(gabm, torch, wl, g, E, steps: int = 2, warmup: int = 1):
             "value": float(E) * wl.K / dt, "unit": "edge-days/s", "kernels": "receiver-tile kernels"}
 
 
+def locations_leg(gabm, torch, wl, g0_ms, steps: int = 2, warmup: int = 1):
+    """The headline population with an agent-location layer on top of its
+    static layers (JUNE-like venues: schools, workplaces, leisure; weights
+    k/64 with k up to 16), differentiable forward+backward with the same
+    checkpoints; Z is raised by the layer's mean weighted degree.  Reports
+    the step time, the layer's own kernel time and its algorithmic bytes,
+    and the size of the clique graph the visits stand for."""
+    import numpy as np
+
+    from synth import location_degree, location_visits
+
+    va, vl, vw, nl = location_visits(wl.pop, np.random.default_rng(0x10C))
+    V = len(va)
+    deg = location_degree(wl.n_agents, (va, vl, vw))
+    Z = (wl.Z + np.float32(wl.tau_I * deg.mean())).astype(np.float32)
+    sizes = np.bincount(vl, minlength=nl).astype(np.int64)
+    expanded = int(np.sum(sizes * (sizes - 1)))
+    g = gabm.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, n_age=8,
+                   pop_offsets=wl.pop.pop_offsets, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight,
+                   visits=(va, vl, vw), n_locations=nl)
+    tgt = load_target(wl.name, wl.K)
+    t = None if tgt is None else torch.tensor(tgt, device="cuda")
+    sim = gabm.Simulator(g, K=wl.K, Z=Z, mode=gabm.HARD_ST, ckpt_every=wl.ckpt_every, tau_g=wl.tau_g,
+                         time_kernels=TIME_EVERY)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    for _ in range(warmup):
+        sim.forward(pb, seed=wl.seed, target=t)
+        sim.backward(pb, seed=wl.seed)
+    torch.cuda.synchronize()
+    sim.kernel_times(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.forward(pb, seed=wl.seed, target=t)
+        sim.backward(pb, seed=wl.seed)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kt = sim.kernel_times(reset=True)["loc"]
+    del sim
+    avg = kt["ms"] / kt["launches"] * 1e-3
+    ck = wl.ckpt_every
+    n_seg = (wl.K + ck - 1) // ck if ck else 1
+    per_step = 2 * wl.K + (n_seg - 1) * ck
+    # one pass: visits read twice (location order: location, agent, weight;
+    # agent order: location, weight) with a 4-byte value and an 8-byte
+    # pressure read per visit; per agent its visit offset, its value and a
+    # read-modify-write of its sum; per location the clearing and one atomic
+    ab = 28.0 * V + 28.0 * wl.n_agents + 24.0 * nl
+    return {"workload": f"{wl.name} + agent-location layer: {V} visits to {nl} venues (schools, workplaces, "
+                        f"leisure), standing for {expanded} directed contacts",
+            "visits": V, "locations": nl, "expanded_contacts": expanded, "ms_per_step": dt * 1e3,
+            "ms_per_step_without_layer": g0_ms,
+            "loc_pass": {"launches_per_step": per_step, "avg_ms": avg * 1e3, "ms_per_step": avg * 1e3 * per_step,
+                         "alg_bytes_per_launch": ab, "alg_GBps": ab / avg / 1e9},
+            "timing": f"eager launches; HIP events around every {TIME_EVERY}th launch of each kernel class"}
+
+
 def cpu_baseline_table():
     """The cpu_baseline leg over every workload: the oracle timed on this host, single thread: C1, C2, C3 and the packed
     populations (C4b, population by population) in full, and 4 of the 128
@@ -480,7 +536,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-days", type=int, default=30)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched (c4a) legs")
-    ap.add_argument("--only", choices=["diff", "plain", "copy", "batched"], default=None,
+    ap.add_argument("--only", choices=["diff", "plain", "copy", "batched", "locations"], default=None,
                     help="run a single leg (for profiler runs)")
     ap.add_argument("--traffic-from", default=None, metavar="DIR",
                     help="no run: turn the rocprofv3 --pmc runs under DIR (fetch/ write/ copy_fetch/ copy_write/) "
@@ -575,6 +631,9 @@ def main():
 
     res = {}
     medians = []
+    if args.only == "locations":
+        print(json.dumps({"location_layer": locations_leg(gabm, torch, wl, None)}), flush=True)
+        return
     # kernel schedule picked by the library's autotuner (a few timed forward days per schedule)
     pp = dict(n_sets=wl.n_sets, per_pop_params=wl.per_pop_params)
     sched, sched_ms = gabm.autotune(g, R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=K, mode=gabm.HARD_ST, **pp,
@@ -622,6 +681,9 @@ def main():
                  f"{res['calibration']['loss_first']:.4g} -> {res['calibration']['loss_last']:.4g}")
         res["profile"] = profile_leg(gabm, torch, wl, g, E)
         note(f"profile leg: {res['profile']['ms_per_step']:.1f} ms per step")
+        res["locations"] = locations_leg(gabm, torch, wl, res["diff_s"] * 1e3)
+        note(f"locations leg: {res['locations']['ms_per_step']:.1f} ms per step, layer "
+             f"{res['locations']['loc_pass']['ms_per_step']:.2f} ms")
         res["c1"] = c1_leg(gabm, torch, args.steps, args.warmup)
         note(f"c1 plain forward (f64): {res['c1']['graph']['ms_per_run']:.3f} ms per run with hipGraphs")
 
@@ -709,6 +771,8 @@ def main():
         out["calibration"] = res["calibration"]
     if "profile" in res:
         out["infectiousness_profile"] = res["profile"]
+    if "locations" in res:
+        out["location_layer"] = res["locations"]
     out["paper_context"] = ("paper: 800k agents, 5M interactions, 133 steps forward in 4 s on a GPU "
                             "(Tesla V100 listed) = 1.66e8 interaction-steps/s; 60 s on CPU (Xeon E7-4850)")
     print(json.dumps(out), flush=True)
