@@ -71,6 +71,25 @@ double ora_uniform(uint64_t seed, uint32_t idx, uint32_t day, uint32_t tag, uint
   return to_unit(o[0]);
 }
 
+/* Gumbel-max (Gumbel 1954; the sampling view of Jang, Gu & Poole 2017): the
+ * index maximising lw[k] + G_k with G_k = -log(-log u_k) is distributed as
+ * softmax(lw); the first maximum wins a tie. */
+int32_t ora_dwell_draw(const float *lw, int32_t n, uint64_t seed, uint32_t idx, uint32_t day, uint32_t tag0,
+                       uint32_t pop, uint32_t stream) {
+  uint32_t o[4];
+  int32_t best = 0;
+  double bv = -INFINITY;
+  for (int32_t k = 0; k < n; ++k) {
+    if (k % 4 == 0) draw(seed, idx, day, tag0 + (uint32_t)(k / 4), pop, stream, o);
+    double v = (double)lw[k] - log(-log(to_unit(o[k % 4])));
+    if (v > bv) {
+      bv = v;
+      best = k;
+    }
+  }
+  return best + 1;
+}
+
 /* Daily random-contact layer: G(n, M) with M = round(n*mean/2) undirected
  * pairs, endpoints from words 0 and 1 by exact 32x32->64 multiplication. */
 int64_t ora_er_pairs(int32_t n_pop, double mean_deg, uint64_t seed, uint32_t day, uint32_t pop,
@@ -132,6 +151,9 @@ typedef struct {
   double *A;    /* [n] */
   double *dA;   /* [ndir*n] */
   uint8_t *stage, *timer;
+  uint8_t *dE, *dI;  /* [W*n] dwell lengths of an exposure on day u, at slot u mod W */
+  uint8_t *dI0;      /* [n] I length of an initial infection */
+  int32_t *eday;     /* [n] exposure day of the hard state */
   int32_t *pop_of, *local;
   int32_t *er_a, *er_b;
 } ws_t;
@@ -139,6 +161,7 @@ typedef struct {
 static void ws_free(ws_t *w) {
   free(w->xi); free(w->dxi); free(w->Sv); free(w->dSv); free(w->x0); free(w->dx0);
   free(w->inf); free(w->dinf); free(w->A); free(w->dA); free(w->stage); free(w->timer);
+  free(w->dE); free(w->dI); free(w->dI0); free(w->eday);
   free(w->pop_of); free(w->local); free(w->er_a); free(w->er_b);
 }
 
@@ -185,6 +208,8 @@ int ora_run(const ora_cfg *c, ora_out *o) {
   if (relaxed_needed && !(c->i0 > 0.f && c->i0 < 1.f)) return -4;
   if (mode == ORA_PLAIN && nd > 0) return -5;
   if (c->pop_offsets[0] != 0 || c->pop_offsets[c->n_pops] != n) return -6;
+  const int dwell = c->dwell_E != NULL || c->dwell_I != NULL;
+  if (dwell && (!c->dwell_E || !c->dwell_I || tE > 8 || tI > 8 || c->iota)) return -8;
 
   const double TE = c->T[ORA_E], TI = c->T[ORA_I];
   const double m = c->m, i0 = c->i0, tau = c->tau_g;
@@ -201,6 +226,10 @@ int ora_run(const ora_cfg *c, ora_out *o) {
   ws.A = calloc(n, sizeof(double));
   ws.stage = calloc(n, 1);
   ws.timer = calloc(n, 1);
+  ws.dE = calloc((size_t)W * n, 1);
+  ws.dI = calloc((size_t)W * n, 1);
+  ws.dI0 = calloc(n, 1);
+  ws.eday = calloc(n, sizeof(int32_t));
   ws.pop_of = calloc(n, sizeof(int32_t));
   ws.local = calloc(n, sizeof(int32_t));
   int64_t er_cap = 16;
@@ -219,6 +248,7 @@ int ora_run(const ora_cfg *c, ora_out *o) {
     ws.dA = calloc((size_t)nd * n, sizeof(double));
   }
   if (!ws.xi || !ws.Sv || !ws.x0 || !ws.inf || !ws.A || !ws.stage || !ws.timer || !ws.pop_of || !ws.local ||
+      !ws.dE || !ws.dI || !ws.dI0 || !ws.eday ||
       !ws.er_a || !ws.er_b || (nd > 0 && (!ws.dxi || !ws.dSv || !ws.dx0 || !ws.dinf || !ws.dA))) {
     ws_free(&ws);
     return -7;
@@ -238,8 +268,11 @@ int ora_run(const ora_cfg *c, ora_out *o) {
     uint32_t pid = (uint32_t)(c->pop_id_base + ws.pop_of[i]);
     double u = ora_uniform(c->seed, (uint32_t)ws.local[i], 0xFFFFFFFFu, ORA_TAG_INIT, pid, c->stream);
     int hard = u < i0;
+    ws.dI0[i] = (uint8_t)(dwell ? ora_dwell_draw(c->dwell_I, tI, c->seed, (uint32_t)ws.local[i], 0xFFFFFFFFu,
+                                                 ORA_TAG_DWELL_I, pid, c->stream)
+                                : tI);
     ws.stage[i] = hard ? ORA_I : ORA_S;
-    ws.timer[i] = hard ? (uint8_t)tI : 0;
+    ws.timer[i] = hard ? ws.dI0[i] : 0;
     double y0 = 0.0, dy0 = 0.0;
     if (relaxed_needed) {
       double z = (log(i0) - log1p(-i0) + logistic_noise(u)) / tau;
@@ -271,10 +304,12 @@ int ora_run(const ora_cfg *c, ora_out *o) {
         for (int32_t k_ = 1; k_ <= W; ++k_) {                                               \
           int32_t u_ = (tt) - k_;                                                           \
           if (u_ < 0) break;                                                                \
-          double xv = ws.xi[(size_t)(u_ % W) * n + i_];                                     \
-          if (k_ <= tE) sE += xv; else sI += xv;                                            \
+          size_t sl_ = (size_t)(u_ % W) * n + i_;                                           \
+          if (k_ > ws.dE[sl_] + ws.dI[sl_]) continue;                                       \
+          double xv = ws.xi[sl_];                                                           \
+          if (k_ <= ws.dE[sl_]) sE += xv; else sI += xv;                                    \
         }                                                                                   \
-        if ((tt) < tI) sI += ws.x0[i_];                                                     \
+        if ((tt) < ws.dI0[i_]) sI += ws.x0[i_];                                             \
       }                                                                                     \
       double rm = (double)n - sS - sE - sI;                                                 \
       cc[ORA_S] = sS; cc[ORA_E] = sE; cc[ORA_I] = sI;                                       \
@@ -295,10 +330,12 @@ int ora_run(const ora_cfg *c, ora_out *o) {
       for (int32_t k = 1; k <= W; ++k) {
         int32_t u = t - k;
         if (u < 0) break;
-        double xv = ws.xi[(size_t)(u % W) * n + j];
-        if (k <= tE) { wE += xv; pE += IOTA(k) * xv; } else { wI += xv; pI += IOTA(k) * xv; }
+        size_t sl = (size_t)(u % W) * n + j;
+        if (k > ws.dE[sl] + ws.dI[sl]) continue; /* that exposure has left I */
+        double xv = ws.xi[sl];
+        if (k <= ws.dE[sl]) { wE += xv; pE += IOTA(k) * xv; } else { wI += xv; pI += IOTA(k) * xv; }
       }
-      if (t < tI) { wI += ws.x0[j]; pI += IOTA(t + tE + 1) * ws.x0[j]; }
+      if (t < ws.dI0[j]) { wI += ws.x0[j]; pI += IOTA(t + tE + 1) * ws.x0[j]; }
       double win = TE * wE + TI * wI;
       double pwin = TE * pE + TI * pI;
       if (mode == ORA_SOFT) {
@@ -315,10 +352,12 @@ int ora_run(const ora_cfg *c, ora_out *o) {
         for (int32_t k = 1; k <= W; ++k) {
           int32_t u = t - k;
           if (u < 0) break;
-          double xv = IOTA(k) * dx[(size_t)(u % W) * n + j];
-          if (k <= tE) dE += xv; else dI += xv;
+          size_t sl = (size_t)(u % W) * n + j;
+          if (k > ws.dE[sl] + ws.dI[sl]) continue;
+          double xv = IOTA(k) * dx[sl];
+          if (k <= ws.dE[sl]) dE += xv; else dI += xv;
         }
-        if (t < tI) dI += IOTA(t + tE + 1) * ws.dx0[(size_t)d * n + j];
+        if (t < ws.dI0[j]) dI += IOTA(t + tE + 1) * ws.dx0[(size_t)d * n + j];
         ws.dinf[(size_t)d * n + j] = TE * dE + TI * dI;
       }
     }
@@ -330,7 +369,22 @@ int ora_run(const ora_cfg *c, ora_out *o) {
     /* removals on day t in the exposure-window form: exposures of day t-W and
      * the initial infections on day tau_I - 1 */
     double drm_w = 0.0;
-    {
+    if (dwell) {
+      /* the exposures of day u leave I on day u + dE + dI; initial infections on day dI0 - 1 */
+      for (int32_t d = 0; d < nd; ++d) drm_dir[d] = 0.0;
+      for (int32_t i = 0; i < n; ++i) {
+        for (int32_t k = 1; k <= W && t - k >= 0; ++k) {
+          size_t sl = (size_t)((t - k) % W) * n + i;
+          if (ws.dE[sl] + ws.dI[sl] != k) continue;
+          drm_w += ws.xi[sl];
+          for (int32_t d = 0; d < nd; ++d) drm_dir[d] += ws.dxi[(size_t)d * W * n + sl];
+        }
+        if (t == ws.dI0[i] - 1) {
+          drm_w += ws.x0[i];
+          for (int32_t d = 0; d < nd; ++d) drm_dir[d] += ws.dx0[(size_t)d * n + i];
+        }
+      }
+    } else {
       int32_t u = t - W;
       if (u >= 0)
         for (int32_t i = 0; i < n; ++i) drm_w += ws.xi[(size_t)(u % W) * n + i];
@@ -376,6 +430,13 @@ int ora_run(const ora_cfg *c, ora_out *o) {
       }
       ws.Sv[i] = Sv - xi;
       ws.xi[slot] = xi; /* overwrites xi^{t-W}, already used above */
+      /* the lengths an exposure of agent i on day t takes (drawn whether or not it happens) */
+      ws.dE[slot] = (uint8_t)(dwell ? ora_dwell_draw(c->dwell_E, tE, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
+                                                    ORA_TAG_DWELL_E, pid, c->stream)
+                                    : tE);
+      ws.dI[slot] = (uint8_t)(dwell ? ora_dwell_draw(c->dwell_I, tI, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
+                                                    ORA_TAG_DWELL_I, pid, c->stream)
+                                    : tI);
 
       /* ---- Progress (hard stage machine) ---- */
       if (mode != ORA_SOFT) {
@@ -385,7 +446,7 @@ int ora_run(const ora_cfg *c, ora_out *o) {
           if (ws.timer[i] == 0) {
             if (st == ORA_E) {
               ws.stage[i] = ORA_I;
-              ws.timer[i] = (uint8_t)tI;
+              ws.timer[i] = ws.dI[(size_t)(ws.eday[i] % W) * n + i];
             } else {
               double um = ora_uniform(c->seed, (uint32_t)ws.local[i], (uint32_t)t, ORA_TAG_MORT, pid, c->stream);
               ws.stage[i] = um < m ? ORA_M : ORA_R;
@@ -394,7 +455,8 @@ int ora_run(const ora_cfg *c, ora_out *o) {
           }
         } else if (st == ORA_S && hard) {
           ws.stage[i] = ORA_E;
-          ws.timer[i] = (uint8_t)tE;
+          ws.timer[i] = ws.dE[slot];
+          ws.eday[i] = t;
         }
       }
     }

@@ -32,6 +32,9 @@ extern "C" {
 
 enum { ORA_S = 0, ORA_E = 1, ORA_I = 2, ORA_R = 3, ORA_M = 4 };
 enum { ORA_TAG_INIT = 0, ORA_TAG_INFECT = 1, ORA_TAG_MORT = 2, ORA_TAG_ER = 3 };
+/* dwell-time draws: uniform k of a draw is word k mod 4 of the block with tag
+ * (base + k / 4), so an E draw uses tags 4-5 and an I draw tags 6-7 */
+enum { ORA_TAG_DWELL_E = 4, ORA_TAG_DWELL_I = 6 };
 enum { ORA_PLAIN = 0, ORA_HARD_ST = 1, ORA_SOFT = 2 };
 
 typedef struct {
@@ -72,6 +75,14 @@ typedef struct {
   const int32_t *visit_agent, *visit_loc;
   const float *visit_w;
   double *loc_p;              /* [n_locations] scratch, or NULL when n_visits = 0 */
+  /* stochastic dwell times (stage transition times drawn from discrete
+   * distributions, Section 3.1; more complex progression, Section 6): log
+   * weights of the lengths 1..tau_E of E and 1..tau_I of I (tau_E, tau_I <= 8
+   * are then the longest lengths), or NULL for the fixed tau_E / tau_I.  Each
+   * exposure of agent i on day u has its lengths drawn by Gumbel-max with the
+   * uniforms of (i, u); an initial infection's I length uses day 2^32 - 1.
+   * Not combined with an infectiousness profile. */
+  const float *dwell_E, *dwell_I;
 } ora_cfg;
 
 typedef struct {
@@ -90,6 +101,9 @@ typedef struct {
 } ora_out;
 
 void ora_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* the Gumbel-max draw of a length in 1..n from log weights lw[n] */
+int32_t ora_dwell_draw(const float *lw, int32_t n, uint64_t seed, uint32_t idx, uint32_t day, uint32_t tag0,
+                       uint32_t pop, uint32_t stream);
 double ora_uniform(uint64_t seed, uint32_t idx, uint32_t day, uint32_t tag, uint32_t pop, uint32_t stream);
 int64_t ora_er_pairs(int32_t n_pop, double mean_deg, uint64_t seed, uint32_t day, uint32_t pop,
                      uint32_t stream, int32_t *a, int32_t *b, int64_t cap);

@@ -41,7 +41,7 @@ class _Cfg(C.Structure):
         ("ndir", C.c_int32), ("dR", C.c_void_p), ("dS", C.c_void_p), ("dm", C.c_void_p), ("di0", C.c_void_p),
         ("iota", C.c_void_p),
         ("n_locations", C.c_int32), ("n_visits", C.c_int64), ("visit_agent", C.c_void_p), ("visit_loc", C.c_void_p),
-        ("visit_w", C.c_void_p), ("loc_p", C.c_void_p),
+        ("visit_w", C.c_void_p), ("loc_p", C.c_void_p), ("dwell_E", C.c_void_p), ("dwell_I", C.c_void_p),
     ]
 
 
@@ -65,6 +65,9 @@ def lib():
         _lib.ora_er_pairs.argtypes = [C.c_int32, C.c_double, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                       C.c_void_p, C.c_void_p, C.c_int64]
         _lib.ora_er_pairs.restype = C.c_int64
+        _lib.ora_dwell_draw.argtypes = [C.c_void_p, C.c_int32, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint32, C.c_uint32]
+        _lib.ora_dwell_draw.restype = C.c_int32
     return _lib
 
 
@@ -82,6 +85,16 @@ def philox(ctr, key) -> np.ndarray:
 
 def uniform(seed: int, idx: int, day: int, tag: int, pop: int = 0, stream: int = 0) -> float:
     return lib().ora_uniform(seed, idx, day, tag, pop, stream)
+
+
+TAG_DWELL_E, TAG_DWELL_I = 4, 6
+
+
+def dwell_draw(log_weights, seed: int, idx: int, day: int, tag: int, pop: int = 0, stream: int = 0) -> int:
+    """The Gumbel-max draw of a length in 1..len(log_weights) for agent idx and
+    day (tag TAG_DWELL_E or TAG_DWELL_I)."""
+    lw = np.ascontiguousarray(log_weights, np.float32)
+    return int(lib().ora_dwell_draw(_p(lw), len(lw), seed, idx & 0xFFFFFFFF, day & 0xFFFFFFFF, tag, pop, stream))
 
 
 def er_pairs(n_pop: int, mean_deg: float, seed: int, day: int, pop: int = 0, stream: int = 0):
@@ -109,7 +122,7 @@ def standard_directions(K: int, n_age: int):
 
 def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), tau_E=3, tau_I=5,
         mode=PLAIN, tau_g=0.5, seed=0, stream=0, pop_id_base=0, er_mean_deg=0.0, er_weight=0.0,
-        target=None, directions=None, want_agents=False, want_stage=False, iota=None, visits=None):
+        target=None, directions=None, want_agents=False, want_stage=False, iota=None, visits=None, dwell=None):
     """Run one simulation.  Parameters are float32 values (widened exactly).
 
     ``iota`` = infectiousness profile over days since exposure ([tau_E +
@@ -119,6 +132,10 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
     ``visits`` = (agent[V], location[V], weight[V]) of the agent-location
     layer, or None: a location's pressure is the weighted sum over its
     visitors, and each visit adds weight * (pressure - own share) to its agent.
+
+    ``dwell`` = (log-weights of the E lengths 1..tau_E, of the I lengths
+    1..tau_I) for stochastic dwell times drawn per exposure by Gumbel-max, or
+    None for the fixed tau_E / tau_I.
 
     ``directions`` = (dR[nd,K], dS[nd,n_age], dm[nd], di0[nd]) or None.
     Returns a dict with counts [K+1,5], drm [K], deaths [K], loss, and when
@@ -160,6 +177,13 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
         cfg.n_locations, cfg.n_visits = nl, len(va)
         cfg.visit_agent, cfg.visit_loc, cfg.visit_w, cfg.loc_p = _p(va), _p(vl), _p(vw), _p(lp)
         keep += [va, vl, vw, lp]
+    if dwell is not None:
+        dE = np.ascontiguousarray(dwell[0], np.float32).reshape(-1)
+        dI = np.ascontiguousarray(dwell[1], np.float32).reshape(-1)
+        if dE.shape[0] != tau_E or dI.shape[0] != tau_I:
+            raise ValueError("dwell tables need tau_E and tau_I values")
+        cfg.dwell_E, cfg.dwell_I = _p(dE), _p(dI)
+        keep += [dE, dI]
     nd = 0
     if directions is not None:
         dR, dS, dm, di0 = (np.ascontiguousarray(x, np.float64) for x in directions)
@@ -189,7 +213,7 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
 
 
 def run_workload(wl, *, mode=None, set_index=0, stream=0, seed=None, R=None, target=None, directions=None,
-                 want_agents=False, want_stage=False, pop_index=None, iota=None, visits=None):
+                 want_agents=False, want_stage=False, pop_index=None, iota=None, visits=None, dwell=None):
     """Run a ``synth`` workload on the oracle (one simulation).  For packed
     populations pass ``pop_index`` to simulate that population alone with its
     own parameter set (populations do not share contacts)."""
@@ -204,10 +228,10 @@ def run_workload(wl, *, mode=None, set_index=0, stream=0, seed=None, R=None, tar
                    tau_I=wl.tau_I, mode=wl.mode if mode is None else mode, tau_g=wl.tau_g,
                    seed=wl.seed if seed is None else seed, stream=stream, pop_id_base=pop_index,
                    er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=target,
-                   directions=directions, want_agents=want_agents, want_stage=want_stage, iota=iota)
+                   directions=directions, want_agents=want_agents, want_stage=want_stage, iota=iota, dwell=dwell)
     return run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K,
                R=wl.R[set_index] if R is None else R, S=wl.S[set_index], m=wl.m[set_index], i0=wl.i0[set_index],
                Z=wl.Z, T=wl.T, tau_E=wl.tau_E, tau_I=wl.tau_I, mode=wl.mode if mode is None else mode,
                tau_g=wl.tau_g, seed=wl.seed if seed is None else seed, stream=stream,
                er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=target, directions=directions,
-               want_agents=want_agents, want_stage=want_stage, iota=iota, visits=visits)
+               want_agents=want_agents, want_stage=want_stage, iota=iota, visits=visits, dwell=dwell)

@@ -307,25 +307,28 @@ def _soft_setup():
     return wl, tgt
 
 
-def _loss(wl, tgt, R, S, m, i0, mode, iota=None):
+def _loss(wl, tgt, R, S, m, i0, mode, iota=None, dwell=None):
     return O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=R, S=S,
                  m=m, i0=i0, Z=wl.Z, mode=mode, tau_g=wl.tau_g, er_mean_deg=wl.er_mean_deg,
-                 er_weight=wl.er_weight, target=tgt, iota=iota)["loss"]
+                 er_weight=wl.er_weight, target=tgt, iota=iota, dwell=dwell)["loss"]
 
 
 # an infectiousness profile over the 8 days after exposure (rising, then
 # falling), values exact in float32
 PROFILE = np.array([0.25, 0.5, 0.75, 1.5, 1.75, 1.25, 0.75, 0.25], np.float32)
+# stochastic dwell times: log weights of the E lengths 1..3 and the I lengths 1..5
+DWELL = (np.log(np.array([0.2, 0.5, 0.3], np.float32)), np.log(np.array([0.1, 0.2, 0.3, 0.25, 0.15], np.float32)))
 
 
-@pytest.mark.parametrize("iota", [None, PROFILE], ids=["flat", "profile"])
-def test_soft_tangents_match_finite_differences(iota):
+@pytest.mark.parametrize("iota,dwell", [(None, None), (PROFILE, None), (None, DWELL)], ids=["flat", "profile", "dwell"])
+def test_soft_tangents_match_finite_differences(iota, dwell):
     wl, tgt = _soft_setup()
     R0, S0, m0, i00 = np.float32(2.5), wl.S[0].copy(), np.float32(0.01), np.float32(0.01)
     dirs = O.standard_directions(wl.K, 8)
-    r = O.run_workload(wl, mode=O.SOFT, R=np.full(wl.K, R0, np.float32), target=tgt, directions=dirs, iota=iota)
+    r = O.run_workload(wl, mode=O.SOFT, R=np.full(wl.K, R0, np.float32), target=tgt, directions=dirs, iota=iota,
+                       dwell=dwell)
     g = r["dL"]
-    assert r["loss"] == pytest.approx(_loss(wl, tgt, R0, S0, m0, i00, O.SOFT, iota), rel=0, abs=0)
+    assert r["loss"] == pytest.approx(_loss(wl, tgt, R0, S0, m0, i00, O.SOFT, iota, dwell), rel=0, abs=0)
 
     def fd(k, h):
         def at(delta):
@@ -338,7 +341,7 @@ def test_soft_tangents_match_finite_differences(iota):
                 m = np.float32(m0 + delta)
             else:
                 i0 = np.float32(i00 + delta)
-            return _loss(wl, tgt, R, S, m, i0, O.SOFT, iota)
+            return _loss(wl, tgt, R, S, m, i0, O.SOFT, iota, dwell)
         d1 = (at(h) - at(-h)) / (2 * h)
         d2 = (at(h / 2) - at(-h / 2)) / h
         return (4 * d2 - d1) / 3  # Richardson
@@ -515,3 +518,116 @@ def test_location_layer_excludes_the_visitor():
         pytest.fail("no seed infects agent 1 alone")
     for t in range(4):
         assert r["A"][t][0] == 0.75 * 0.25 and r["A"][t][1] == 0.0
+
+
+# ---------------------------------------------------------------- stochastic dwell times
+
+
+def test_dwell_draw_frequencies():
+    """The Gumbel-max draw over (agent, day) counters follows softmax of the
+    log weights (chi-square over 40,000 draws), for E and I tables, including
+    a length of weight zero that is never drawn."""
+    lwE = np.log(np.array([0.2, 0.5, 0.3], np.float32))
+    lwI = np.array([np.log(0.1), np.log(0.2), -np.inf, np.log(0.45), np.log(0.25)], np.float32)
+    for lw, tag in ((lwE, O.TAG_DWELL_E), (lwI, O.TAG_DWELL_I)):
+        p = np.exp(lw.astype(np.float64))
+        p /= p.sum()
+        draws = np.array([O.dwell_draw(lw, 11, i, d, tag) for i in range(2000) for d in range(20)])
+        counts = np.bincount(draws - 1, minlength=len(lw))
+        if not np.all(p > 0):
+            assert np.all(counts[p == 0] == 0)
+        keep = p > 0
+        chi2 = np.sum((counts[keep] - p[keep] * len(draws)) ** 2 / (p[keep] * len(draws)))
+        assert stats.chi2.sf(chi2, keep.sum() - 1) > 1e-4, (counts, p)
+    # E and I draws of one exposure are not the same stream
+    e = [O.dwell_draw(np.zeros(8, np.float32), 5, i, 3, O.TAG_DWELL_E) for i in range(200)]
+    i_ = [O.dwell_draw(np.zeros(8, np.float32), 5, i, 3, O.TAG_DWELL_I) for i in range(200)]
+    assert e != i_
+
+
+@pytest.mark.parametrize("mode", [O.PLAIN, O.HARD_ST, O.SOFT], ids=["plain", "hard_st", "soft"])
+def test_one_hot_dwell_tables_are_the_fixed_model(mode):
+    """Tables that put all weight on tau_E and tau_I reproduce the model with
+    fixed dwell times bit for bit: trajectories, sums, loss and tangents."""
+    wl = make_workload("c2", n_agents=3000, K=20)
+    tgt = np.linspace(0.0, 0.5, wl.K)
+    ninf = np.float32(-np.inf)
+    onehot = (np.array([ninf, ninf, 0.0], np.float32), np.array([ninf] * 4 + [0.0], np.float32))
+    dirs = O.standard_directions(wl.K, 8) if mode != O.PLAIN else None
+    a = O.run_workload(wl, mode=mode, target=tgt, directions=dirs, want_agents=True, want_stage=True)
+    b = O.run_workload(wl, mode=mode, target=tgt, directions=dirs, want_agents=True, want_stage=True, dwell=onehot)
+    for k in ("counts", "A", "stage", "drm"):
+        assert np.array_equal(a[k], b[k]), k
+    assert a["loss"] == b["loss"]
+    if dirs is not None:
+        assert np.array_equal(a["dL"], b["dL"])
+
+
+ST_E, ST_I = 1, 2  # stage codes of the exposed and infectious stages
+
+
+def _runs_of(stage_row, value):
+    """(start, length) of each maximal run of `value` in a stage trajectory."""
+    out, start = [], None
+    for t, s in enumerate(stage_row):
+        if s == value and start is None:
+            start = t
+        elif s != value and start is not None:
+            out.append((start, t - start))
+            start = None
+    if start is not None:
+        out.append((start, None))  # still running at the end
+    return out
+
+
+def test_dwell_stage_durations_follow_the_draws():
+    """In a hard run every exposure's E and I spells last exactly the lengths
+    drawn for (agent, exposure day), initial infections' I spells the length
+    drawn for day 2^32 - 1, and the exposure-window form agrees with the stage
+    machine (no mismatch); the E lengths observed over the run follow the
+    table (chi-square)."""
+    wl = make_workload("c2", n_agents=4000, K=40)
+    r = O.run_workload(wl, mode=O.PLAIN, want_stage=True, dwell=DWELL)
+    assert r["mismatch"] == 0
+    st = r["stage"]  # [K+1, N]
+    seen_E = []
+    n_checked = 0
+    for i in range(wl.n_agents):
+        row = st[:, i]
+        if row[0] == ST_I:
+            d0 = O.dwell_draw(DWELL[1], wl.seed, i, 0xFFFFFFFF, O.TAG_DWELL_I)
+            runs = _runs_of(row, ST_I)
+            assert runs[0][0] == 0
+            if runs[0][1] is not None:
+                assert runs[0][1] == d0, (i, runs, d0)
+            continue
+        for start, length in _runs_of(row, ST_E):
+            u = start - 1  # exposed during day u, E from snapshot u + 1
+            dE = O.dwell_draw(DWELL[0], wl.seed, i, u, O.TAG_DWELL_E)
+            dI = O.dwell_draw(DWELL[1], wl.seed, i, u, O.TAG_DWELL_I)
+            if length is None:
+                continue
+            assert length == dE, (i, u, length, dE)
+            seen_E.append(length)
+            irun = [x for x in _runs_of(row, ST_I) if x[0] == start + length]
+            assert irun, (i, u)
+            if irun[0][1] is not None:
+                assert irun[0][1] == dI, (i, u, irun, dI)
+                n_checked += 1
+    assert n_checked > 200
+    p = np.exp(DWELL[0].astype(np.float64))
+    p /= p.sum()
+    counts = np.bincount(np.array(seen_E) - 1, minlength=3)
+    chi2 = np.sum((counts - p * len(seen_E)) ** 2 / (p * len(seen_E)))
+    assert stats.chi2.sf(chi2, 2) > 1e-4, counts
+
+
+def test_dwell_tables_are_checked():
+    wl = make_workload("c1", n_agents=500, K=5)
+    with pytest.raises(ValueError):  # not combined with an infectiousness profile
+        O.run_workload(wl, mode=O.PLAIN, dwell=(np.zeros(3, np.float32), np.zeros(5, np.float32)),
+                       iota=np.ones(8, np.float32))
+    with pytest.raises(ValueError):  # lengths of at most 8 days
+        O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=2.5,
+              S=wl.S[0], m=0.01, i0=0.01, Z=wl.Z, tau_E=9, tau_I=5,
+              dwell=(np.zeros(9, np.float32), np.zeros(5, np.float32)))
