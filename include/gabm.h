@@ -180,6 +180,16 @@ typedef struct {
                           infection counts as exposed on day -tau_E - 1.  B = 1 only (batched runs:
                           GABM_EUNSUPPORTED); a simulation keeps the choice (profile or not) it was
                           created with. */
+  const float *dwell_E; /* stochastic dwell times (Section 3.1: transition times drawn from discrete
+                          distributions; Section 6: stochastic progression): device [tau_E] and
+                          [tau_I] log weights of the E lengths 1..tau_E and the I lengths 1..tau_I
+                          (-inf: never), or both NULL for fixed tau_E / tau_I.  Each exposure of an
+                          agent on day u draws both lengths by Gumbel-max, argmax_k lw[k] -
+                          log(-log u_k), with Philox uniforms of (agent, u) (an initial infection's
+                          I length: day 2^32 - 1); tau_E, tau_I <= 8 (GABM_EINVAL otherwise).  Hard
+                          modes only, no profile, B = 1 (GABM_EUNSUPPORTED otherwise).  NaN weights
+                          are undefined. */
+  const float *dwell_I;
 } gabm_params;
 
 typedef struct {

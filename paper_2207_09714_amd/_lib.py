@@ -57,7 +57,7 @@ class Params(C.Structure):
     _fields_ = [("n_sets", C.c_int32), ("K", C.c_int32), ("tau_E", C.c_int32), ("tau_I", C.c_int32),
                 ("mode", C.c_int32), ("per_pop_params", C.c_int32), ("R", C.c_void_p), ("S", C.c_void_p),
                 ("m", C.c_void_p), ("i0", C.c_void_p), ("Z", C.c_void_p), ("T", C.c_float * 5),
-                ("tau_g", C.c_float), ("iota", C.c_void_p)]
+                ("tau_g", C.c_float), ("iota", C.c_void_p), ("dwell_E", C.c_void_p), ("dwell_I", C.c_void_p)]
 
 
 class Rng(C.Structure):

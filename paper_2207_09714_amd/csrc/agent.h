@@ -17,6 +17,40 @@
 
 namespace gabm {
 
+// Gumbel-max draw of a length in 1..n from log weights lw: the index that
+// maximises lw[k] - log(-log u_k) is distributed as softmax(lw) (first
+// maximum on a tie).  u_k is word k mod 4 of the block with tag tag0 + k / 4.
+__device__ __forceinline__ int dwell_draw(const float* lw, int n, Rng rng, uint32_t loc, uint32_t day, uint32_t tag0,
+                                          uint32_t p, uint32_t stream) {
+  int best = 0;
+  double bv = -INFINITY;
+  uint4 x = make_uint4(0u, 0u, 0u, 0u);
+  for (int k = 0; k < n; ++k) {
+    if ((k & 3) == 0) x = rng_block(rng, loc, day, tag0 + (uint32_t)(k >> 2), p, stream);
+    const uint32_t w = (k & 3) == 0 ? x.x : ((k & 3) == 1 ? x.y : ((k & 3) == 2 ? x.z : x.w));
+    const double v = (double)lw[k] - log(-log(unit_u(w)));
+    if (v > bv) {
+      bv = v;
+      best = k;
+    }
+  }
+  return best + 1;
+}
+
+// E and I lengths of an exposure of agent `loc` (population p) on `day`
+// (kDayInit for an initial infection's I length): drawn when the parameters
+// carry dwell tables, tau_E / tau_I otherwise
+__device__ __forceinline__ int dwell_E(const DParams& P, Rng rng, uint32_t loc, uint32_t day, uint32_t p,
+                                       uint32_t stream) {
+  return P.dwell_E ? dwell_draw(P.dwell_E, P.tau_E, rng, loc, day, TAG_DWELL_E, p, stream) : P.tau_E;
+}
+__device__ __forceinline__ int dwell_I(const DParams& P, Rng rng, uint32_t loc, uint32_t day, uint32_t p,
+                                       uint32_t stream) {
+  return P.dwell_I ? dwell_draw(P.dwell_I, P.tau_I, rng, loc, day, TAG_DWELL_I, p, stream) : P.tau_I;
+}
+// exposure day held in a packed record (-1: none, or an initial infection)
+__device__ __forceinline__ int rec_eday(uint32_t r) { return (int)(int16_t)(r >> 16); }
+
 struct HardDay {
   uint32_t rec;     // next record
   uint32_t newst;   // next stage
@@ -48,7 +82,7 @@ __device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uin
     if (tm == 0) {
       if (st == ST_E) {
         o.newst = ST_I;
-        tm = (uint32_t)P.tau_I;
+        tm = (uint32_t)dwell_I(P, rng, loc, (uint32_t)rec_eday(r), (uint32_t)p, stream);
       } else {
         const double um = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_MORT, (uint32_t)p, stream).x);
         o.newst = um < (double)P.m[set] ? ST_M : ST_R;
@@ -58,7 +92,7 @@ __device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uin
     o.rec = (r & 0xFFFF0000u) | (tm << 8) | o.newst;
   } else if (st == ST_S && o.h) {
     o.newst = ST_E;
-    o.rec = make_rec(ST_E, (uint32_t)P.tau_E, t);
+    o.rec = make_rec(ST_E, (uint32_t)dwell_E(P, rng, loc, (uint32_t)t, (uint32_t)p, stream), t);
   }
   return o;
 }

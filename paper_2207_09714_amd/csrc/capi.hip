@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <string>
 
+#include "agent.h"
 #include "batched.h"
 #include "day_kernels.h"
 #include "sim_internal.h"
@@ -50,6 +51,15 @@ gabm_status check_params(const Graph& G, const gabm_params* p, DParams* out) {
   P.K = p->K; P.tau_E = p->tau_E; P.tau_I = p->tau_I; P.n_age = G.n_age; P.mode = p->mode;
   P.per_pop = p->per_pop_params ? 1 : 0; P.n_sets = p->n_sets;
   P.iota = p->iota;
+  GABM_CHECK((p->dwell_E == nullptr) == (p->dwell_I == nullptr), GABM_EINVAL,
+             "dwell_E and dwell_I are given together or not at all");
+  if (p->dwell_E) {
+    GABM_CHECK(p->tau_E <= 8 && p->tau_I <= 8, GABM_EINVAL, "dwell tables cover at most 8 days each");
+    GABM_CHECK(p->iota == nullptr, GABM_EUNSUPPORTED, "dwell tables are not combined with an infectiousness profile");
+    GABM_CHECK(p->mode != GABM_SOFT, GABM_EUNSUPPORTED, "dwell tables run in the hard modes (PLAIN, HARD_ST)");
+  }
+  P.dwell_E = p->dwell_E;
+  P.dwell_I = p->dwell_I;
   return GABM_OK;
 }
 
@@ -155,7 +165,7 @@ __global__ void k_step_progress(DGraph G, DParams P, int set, Rng rng, uint32_t 
       if (tm == 0) {
         if (st == ST_E) {
           ns = ST_I;
-          tm = (uint32_t)P.tau_I;
+          tm = (uint32_t)dwell_I(P, rng, loc, (uint32_t)rec_eday(r), (uint32_t)p, stream);
         } else {
           const double um = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_MORT, (uint32_t)p, stream).x);
           ns = um < (double)P.m[s] ? ST_M : ST_R;
@@ -165,7 +175,7 @@ __global__ void k_step_progress(DGraph G, DParams P, int set, Rng rng, uint32_t 
       nr = (r & 0xFFFF0000u) | (tm << 8) | ns;
     } else if (st == ST_S && h[i]) {
       ns = ST_E;
-      nr = make_rec(ST_E, (uint32_t)P.tau_E, t);
+      nr = make_rec(ST_E, (uint32_t)dwell_E(P, rng, loc, (uint32_t)t, (uint32_t)p, stream), t);
     }
     rout[i] = nr;
     c[ns] = 1.0;
@@ -416,6 +426,7 @@ static gabm_status check_run(const Graph& G, const gabm_params* p, const gabm_ru
   if (B > 1) {
     GABM_CHECK(p->iota == nullptr, GABM_EUNSUPPORTED, "batched runs take no infectiousness profile");
     GABM_CHECK(G.n_visits == 0, GABM_EUNSUPPORTED, "batched runs take no agent-location layer");
+    GABM_CHECK(p->dwell_E == nullptr, GABM_EUNSUPPORTED, "batched runs take no dwell tables");
     GABM_CHECK(B <= kBMaxB, GABM_EUNSUPPORTED, "a batched run takes at most 256 simulations");
     GABM_CHECK(!p->per_pop_params, GABM_EUNSUPPORTED,
                "batched runs take one parameter set per simulation (per-population parameters need B = 1)");

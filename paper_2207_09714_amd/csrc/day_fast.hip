@@ -445,12 +445,18 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
     const double Sbar1 = (double)a.Sbar[i];
     if (t >= 1) {
       const int d = t - 1;
-      double sE = 0.0, sI = 0.0;
-      for (int k = 1; k <= W; ++k) {
-        const double v = (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
-        if (k <= P.tau_E) sE += v; else sI += v;
+      // E for dE days after exposure on day d, then I until day d + dL
+      int dE = P.tau_E, dL = W;
+      if (P.dwell_E) {
+        dE = dwell_E(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
+        dL = dE + dwell_I(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
       }
-      const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + W] : 0.0;
+      double sE = 0.0, sI = 0.0;
+      for (int k = 1; k <= dL; ++k) {
+        const double v = (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+        if (k <= dE) sE += v; else sI += v;
+      }
+      const double drm_bar = (d + dL < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + dL] : 0.0;
       const uint32_t fl = a.fl_st[i];
       const double Aday = (double)a.A_st[i];
       const AdjOut ad = agent_adjoint<true>(P, a.rng, a.stream, d, set, p, loc, age, Aday, (double)(fl & 1u),
@@ -471,9 +477,9 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
       }
     } else {
       double sI = 0.0;
-      for (int k = 0; k < P.tau_I; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
-      const double x0_bar =
-          P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + P.tau_I - 1] : 0.0) - Sbar1;
+      const int dI0 = dwell_I(P, a.rng, loc, kDayInit, (uint32_t)p, a.stream);
+      for (int k = 0; k < dI0; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
+      const double x0_bar = P.TI * sI + ((dI0 - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + dI0 - 1] : 0.0) - Sbar1;
       const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, a.stream).x);
       double y0, dy0;
       relaxed_init((double)P.i0[set], u, P.tau, y0, dy0);

@@ -64,7 +64,8 @@ __global__ void __launch_bounds__(kBlock) k_init(InitArgs<RT> a) {
       ci = y0;
     } else {
       inf_now = u < i0;
-      a.rec[i] = inf_now ? make_rec(ST_I, (uint32_t)a.P.tau_I, -1) : make_rec(ST_S, 0, -1);
+      a.rec[i] = inf_now ? make_rec(ST_I, (uint32_t)dwell_I(a.P, a.rng, loc, kDayInit, (uint32_t)p, a.stream), -1)
+                         : make_rec(ST_S, 0, -1);
       cs = inf_now ? 0.0 : 1.0;
       ci = inf_now ? 1.0 : 0.0;
     }
@@ -404,13 +405,19 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
       const double m = P.m[set];
       if (t >= 1) {
         const int d = t - 1;
-        // inf_bar over the days after exposure on day d, weighted by the profile
-        double sE = 0.0, sI = 0.0;
-        for (int k = 1; k <= W; ++k) {
-          const double v = iota_at(P, k) * (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
-          if (k <= P.tau_E) sE += v; else sI += v;
+        // inf_bar over the days after exposure on day d (E for dE days, then
+        // I until day d + dL), weighted by the profile
+        int dE = P.tau_E, dL = W;
+        if (P.dwell_E) {
+          dE = dwell_E(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
+          dL = dE + dwell_I(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
         }
-        const double drm_bar = (d + W < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + W] : 0.0;
+        double sE = 0.0, sI = 0.0;
+        for (int k = 1; k <= dL; ++k) {
+          const double v = iota_at(P, k) * (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+          if (k <= dE) sE += v; else sI += v;
+        }
+        const double drm_bar = (d + dL < P.K) ? m * a.Dbar[(int64_t)o * P.K + d + dL] : 0.0;
         const double A = pre_A;
         double Sv, h;
         if (SOFT) {
@@ -439,9 +446,10 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
       } else {
         // initial infections: x0_bar = T_I sum_{t<tau_I} inf_bar^t + m Dbar^{tau_I-1} - Sbar^0
         double sI = 0.0;  // day k is tau_E + 1 + k days after the initial infection's exposure
-        for (int k = 0; k < P.tau_I; ++k) sI += iota_at(P, P.tau_E + 1 + k) * (double)a.ring[(int64_t)(k % W) * G.N + i];
+        const int dI0 = dwell_I(P, a.rng, loc, kDayInit, (uint32_t)p, a.stream);
+        for (int k = 0; k < dI0; ++k) sI += iota_at(P, P.tau_E + 1 + k) * (double)a.ring[(int64_t)(k % W) * G.N + i];
         const double x0_bar =
-            P.TI * sI + ((P.tau_I - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + P.tau_I - 1] : 0.0) - pre_Sbar;
+            P.TI * sI + ((dI0 - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + dI0 - 1] : 0.0) - pre_Sbar;
         const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, a.stream).x);
         double y0, dy0;
         relaxed_init((double)P.i0[set], u, P.tau, y0, dy0);

@@ -39,6 +39,9 @@ constexpr int kChunkShift = 8;
 
 enum : uint32_t { ST_S = 0, ST_E = 1, ST_I = 2, ST_R = 3, ST_M = 4 };
 enum : uint32_t { TAG_INIT = 0, TAG_INFECT = 1, TAG_MORT = 2, TAG_ER = 3 };
+// dwell-time draws: uniform k of a draw is word k mod 4 of the block with tag
+// (base + k / 4); E lengths use tags 4-5, I lengths 6-7
+enum : uint32_t { TAG_DWELL_E = 4, TAG_DWELL_I = 6 };
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -173,6 +176,10 @@ struct DParams {
   double TE, TI, tau;
   int32_t K, tau_E, tau_I, n_age, mode, per_pop, n_sets;
   const float* iota;  // [tau_E + tau_I] infectiousness over days since exposure, or null (flat)
+  // stochastic dwell times: log weights of the lengths 1..tau_E (E) and
+  // 1..tau_I (I), or null for the fixed tau_E / tau_I
+  const float* dwell_E;
+  const float* dwell_I;
 };
 
 // Weight of the k-th day after exposure (k = 1 .. tau_E + tau_I): the

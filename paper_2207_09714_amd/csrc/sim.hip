@@ -773,14 +773,15 @@ static void run_backward(Sim& s, const DParams& P, Rng rng, uint32_t stream, con
 // captured or direct execution of a run function
 template <class F>
 static gabm_status execute(Sim& s, bool fwd, const void* k1, const void* k2, const void* k3, const void* k4,
-                           const void* k5, const void* k6, const void* k7, hipStream_t st, F f) {
+                           const void* k5, const void* k6, const void* k7, const void* k8, const void* k9,
+                           hipStream_t st, F f) {
   if (!s.use_graph) {
     f(st);
     GABM_HIP(hipGetLastError());
     return GABM_OK;
   }
   auto& cache = fwd ? s.fwd_graphs : s.bwd_graphs;
-  auto key = std::make_tuple(k1, k2, k3, k4, k5, k6, k7);
+  auto key = std::make_tuple(k1, k2, k3, k4, k5, k6, k7, k8, k9);
   auto it = cache.find(key);
   if (it == cache.end()) {
     hipStream_t cs = st;
@@ -821,12 +822,12 @@ gabm_status sim_forward(Sim& s, const DParams& P, const gabm_rng* r, const doubl
   if (s.precision == GABM_F64)
     rc = execute(s, true, P.R, P.S, target, out ? out->counts : nullptr, out ? out->loss : nullptr,
                  (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, P.dwell_E, P.dwell_I, st,
                  [&](hipStream_t cs) { run_forward<double>(s, P, rng, stream, target, stride, out, cs); });
   else
     rc = execute(s, true, P.R, P.S, target, out ? out->counts : nullptr, out ? out->loss : nullptr,
                  (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^ ((uint64_t)stride << 56) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, P.dwell_E, P.dwell_I, st,
                  [&](hipStream_t cs) { run_forward<float>(s, P, rng, stream, target, stride, out, cs); });
   if (rc == GABM_OK) {
     s.fwd_done = true;
@@ -848,11 +849,11 @@ gabm_status sim_backward(Sim& s, const DParams& P, const gabm_rng* r, const doub
   if (s.precision == GABM_F64)
     return execute(s, false, P.R, lw, db, out->dR, out->di0,
                    (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, P.dwell_E, P.dwell_I, st,
                    [&](hipStream_t cs) { run_backward<double>(s, P, rng, stream, lw, db, out, cs); });
   return execute(s, false, P.R, lw, db, out->dR, out->di0,
                  (const void*)(uintptr_t)(r->seed ^ ((uint64_t)r->replicate << 40) ^
-                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, st,
+                                          ((uint64_t)(r->independent_sets ? 1 : 0) << 63)), P.iota, P.dwell_E, P.dwell_I, st,
                  [&](hipStream_t cs) { run_backward<float>(s, P, rng, stream, lw, db, out, cs); });
 }
 

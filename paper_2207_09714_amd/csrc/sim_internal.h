@@ -91,7 +91,8 @@ struct Sim {
   bool fwd_done = false;
 
   // captured graphs, keyed by the call's pointers
-  std::map<std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, const void*>,
+  std::map<std::tuple<const void*, const void*, const void*, const void*, const void*, const void*, const void*,
+                      const void*, const void*>,
            hipGraphExec_t>
       fwd_graphs, bwd_graphs;
 

@@ -142,7 +142,7 @@ class ParamBlock:
     """gabm_params with the device tensors it points to kept alive."""
 
     def __init__(self, *, R, S, m, i0, Z, K, n_sets, tau_E=3, tau_I=5, mode=HARD_ST, per_pop_params=False,
-                 T=(0, 0, 1, 0, 0), tau_g=0.5, iota=None):
+                 T=(0, 0, 1, 0, 0), tau_g=0.5, iota=None, dwell=None):
         dev = _dev()
         self.R = _on_dev(R, torch.float32, dev).reshape(n_sets, K)
         self.S = _on_dev(S, torch.float32, dev).reshape(n_sets, -1)
@@ -163,6 +163,15 @@ class ParamBlock:
         if self.iota is not None and self.iota.numel() != tau_E + tau_I:
             raise ValueError("iota needs tau_E + tau_I values")
         p.iota = None if self.iota is None else self.iota.data_ptr()
+        # stochastic dwell times: (log weights of E lengths 1..tau_E, of I lengths 1..tau_I)
+        self.dwell = None
+        if dwell is not None:
+            dE = _on_dev(dwell[0], torch.float32, dev).reshape(-1)
+            dI = _on_dev(dwell[1], torch.float32, dev).reshape(-1)
+            if dE.numel() != tau_E or dI.numel() != tau_I:
+                raise ValueError("dwell tables need tau_E and tau_I values")
+            self.dwell = (dE, dI)
+            p.dwell_E, p.dwell_I = dE.data_ptr(), dI.data_ptr()
         self.c = p
 
 
@@ -239,12 +248,12 @@ class Simulator:
 
     def __init__(self, graph: Graph, *, n_sets=1, K, Z, tau_E=3, tau_I=5, mode=HARD_ST, n_reps=1,
                  per_pop_params=False, ckpt_every=0, precision=F32, use_hip_graph=False, T=(0, 0, 1, 0, 0),
-                 tau_g=0.5, time_kernels=False, schedule=0, iota=None):
+                 tau_g=0.5, time_kernels=False, schedule=0, iota=None, dwell=None):
         self.graph = graph
         self.n_sets, self.K, self.n_reps = int(n_sets), int(K), int(n_reps)
         self.per_pop = bool(per_pop_params)
         self.layout = dict(K=K, n_sets=n_sets, tau_E=tau_E, tau_I=tau_I, mode=mode, per_pop_params=per_pop_params,
-                           T=T, tau_g=tau_g, iota=iota)
+                           T=T, tau_g=tau_g, iota=iota, dwell=dwell)
         self.Z = Z
         self.n_out = self.n_reps * (graph.n_pops if self.per_pop else self.n_sets)
         zeros = torch.zeros(self.n_sets * max(K, graph.n_age), device=_dev())
