@@ -59,6 +59,9 @@ struct HardDay {
   bool was_s;       // susceptible at the start of the day
 };
 
+// DWELL = false compiles the fixed tau_E / tau_I only (callers that never
+// take dwell tables)
+template <bool DWELL = true>
 __device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uint32_t stream, int t, int set, int p,
                                                   uint32_t loc, int age, double A, uint32_t r, double* lam_out) {
   const double Rt = P.R[set * P.K + t], Sa = P.S[set * P.n_age + age], Zp = P.Z[p];
@@ -82,7 +85,7 @@ __device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uin
     if (tm == 0) {
       if (st == ST_E) {
         o.newst = ST_I;
-        tm = (uint32_t)dwell_I(P, rng, loc, (uint32_t)rec_eday(r), (uint32_t)p, stream);
+        tm = DWELL ? (uint32_t)dwell_I(P, rng, loc, (uint32_t)rec_eday(r), (uint32_t)p, stream) : (uint32_t)P.tau_I;
       } else {
         const double um = unit_u(rng_block(rng, loc, (uint32_t)t, TAG_MORT, (uint32_t)p, stream).x);
         o.newst = um < (double)P.m[set] ? ST_M : ST_R;
@@ -92,7 +95,8 @@ __device__ __forceinline__ HardDay hard_agent_day(const DParams& P, Rng rng, uin
     o.rec = (r & 0xFFFF0000u) | (tm << 8) | o.newst;
   } else if (st == ST_S && o.h) {
     o.newst = ST_E;
-    o.rec = make_rec(ST_E, (uint32_t)dwell_E(P, rng, loc, (uint32_t)t, (uint32_t)p, stream), t);
+    o.rec = make_rec(ST_E, DWELL ? (uint32_t)dwell_E(P, rng, loc, (uint32_t)t, (uint32_t)p, stream) : (uint32_t)P.tau_E,
+                     t);
   }
   return o;
 }

@@ -188,7 +188,7 @@ __device__ __forceinline__ void fwd_agent(const BFwdArgs& a, const Slots<SPL>& s
     if (sl.ok[s]) {
       const int64_t idx = (int64_t)r * S.B + sl.b[s];
       const double A = P.TI * aI[s] + (withE ? P.TE * aE[s] : 0.0);
-      const HardDay hd = hard_agent_day(P, a.rng, sl.strm[s], a.t, sl.set[s], p, loc, age, A, a.rec_in[idx], nullptr);
+      const HardDay hd = hard_agent_day<false>(P, a.rng, sl.strm[s], a.t, sl.set[s], p, loc, age, A, a.rec_in[idx], nullptr);
       a.rec_out[idx] = hd.rec;
       const int64_t sidx = IL ? il_index<SPL>(r, gl, s) : idx;
       if (a.A_st) a.A_st[sidx] = (float)A;

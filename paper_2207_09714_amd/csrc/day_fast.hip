@@ -343,7 +343,7 @@ __device__ __forceinline__ double gathered(const SliceSums& ga, int i) {
 // day t+1, counts.  Packed populations: each agent uses its population's
 // normaliser and parameter set and counts into its output; a block whose
 // agents share one output reduces its counts first.
-template <bool POPS>
+template <bool POPS, bool DWELL>
 __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSums ga) {
   __shared__ unsigned scnt[kCnt];
   const int tid = threadIdx.x;
@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
       a.A_er[i] = 0.0;
     }
     if (a.A_st) a.A_st[i] = (float)A;
-    const HardDay hd = hard_agent_day(P, a.rng, a.stream, t, set, p, loc, G.age[i], A, a.rec_in[i], nullptr);
+    const HardDay hd = hard_agent_day<DWELL>(P, a.rng, a.stream, t, set, p, loc, G.age[i], A, a.rec_in[i], nullptr);
     if (a.fl_st) a.fl_st[i] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
     newst = hd.newst;
     removed = hd.removed;
@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
 // then the adjoint of day t-1 (t >= 1) or of the initial infections (t = 0);
 // g^{t-1} and its non-zero mask for the next step's gather.  Parameter-gradient
 // partials are reduced per block when its agents share one parameter set.
-template <bool POPS>
+template <bool POPS, bool DWELL>
 __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga) {
   __shared__ double sg[2 + 16];
   const int tid = threadIdx.x;
@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
       const int d = t - 1;
       // E for dE days after exposure on day d, then I until day d + dL
       int dE = P.tau_E, dL = W;
-      if (P.dwell_E) {
+      if (DWELL && P.dwell_E) {
         dE = dwell_E(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
         dL = dE + dwell_I(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
       }
@@ -477,7 +477,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
       }
     } else {
       double sI = 0.0;
-      const int dI0 = dwell_I(P, a.rng, loc, kDayInit, (uint32_t)p, a.stream);
+      const int dI0 = DWELL ? dwell_I(P, a.rng, loc, kDayInit, (uint32_t)p, a.stream) : P.tau_I;
       for (int k = 0; k < dI0; ++k) sI += (double)a.ring[(int64_t)(k % W) * G.N + i];
       const double x0_bar = P.TI * sI + ((dI0 - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + dI0 - 1] : 0.0) - Sbar1;
       const double u = unit_u(rng_block(a.rng, loc, kDayInit, TAG_INIT, (uint32_t)p, a.stream).x);
@@ -504,10 +504,14 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
   }
 }
 
-template __global__ void k_agent_fwd<false>(FwdArgs<float>, SliceSums);
-template __global__ void k_agent_fwd<true>(FwdArgs<float>, SliceSums);
-template __global__ void k_agent_bwd<false>(BwdArgs<float>, FastMasks, SliceSums);
-template __global__ void k_agent_bwd<true>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_fwd<false, false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true, false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<false, true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true, true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_bwd<false, false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true, false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<false, true>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true, true>(BwdArgs<float>, FastMasks, SliceSums);
 template __global__ void k_gather_fast<false>(GatherArgs);
 template __global__ void k_gather_fast<true>(GatherArgs);
 

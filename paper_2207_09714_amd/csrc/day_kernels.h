@@ -168,9 +168,10 @@ inline SliceSums slice_sums(const GatherArgs& a) {
 template <bool BWD>
 __global__ void k_gather_fast(GatherArgs a);
 // POPS: several populations (per-agent population, parameter set and output)
-template <bool POPS>
+// DWELL: the parameters may carry stochastic dwell tables
+template <bool POPS, bool DWELL>
 __global__ void k_agent_fwd(FwdArgs<float> a, SliceSums ga);
-template <bool POPS>
+template <bool POPS, bool DWELL>
 __global__ void k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga);
 __global__ void k_fin_fwd(FinArgs a);
 __global__ void k_dbar_eff(int n_out, int K, const double* Dbar, const double* w, const double* db, double* out);

@@ -53,7 +53,7 @@ struct LocVecVal {
   __device__ __forceinline__ double at(int c) const { return (double)v[c]; }
 };
 
-// P must be zero on entry.  Each wave takes 64 consecutive location-sorted
+// P must be zero on entry (the previous pass's k_loc_gather clears it).  Each wave takes 64 consecutive location-sorted
 // visits; a segmented scan over the wave (runs of one location are
 // contiguous) leaves each run's total in its last lane, which adds it to P_l:
 // one atomic per location and wave.
@@ -85,11 +85,15 @@ __global__ void __launch_bounds__(kBlock) k_loc_pressure(LocView L, V val, doubl
 // agent (an agent has a handful of visits).  The visitor's own share is
 // formed with the same product as in the pressure pass and subtracted
 // before the multiplication, without contraction, so an agent never meets
-// itself.
+// itself.  The pressures alternate between two buffers: this pass also
+// clears `P_next`, the one the next pass accumulates into, which saves a
+// separate clearing launch per pass.
 template <class V>
-__global__ void __launch_bounds__(kBlock) k_loc_gather(LocView L, V val, const double* P, double* acc) {
+__global__ void __launch_bounds__(kBlock) k_loc_gather(LocView L, V val, const double* P, double* acc,
+                                                       double* P_next) {
 #pragma clang fp contract(off)
   const int64_t stride = (int64_t)gridDim.x * kBlock;
+  for (int64_t l = (int64_t)blockIdx.x * kBlock + threadIdx.x; l < L.n_loc; l += stride) P_next[l] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < L.N; i += stride) {
     const int64_t b = L.av_ptr[i], e = L.av_ptr[i + 1];
     if (b == e) continue;

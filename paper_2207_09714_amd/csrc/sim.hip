@@ -123,7 +123,7 @@ static Layout layout(const Graph& G, int B, int64_t NVs, int n_out, int n_sets, 
   L.sbar = diff ? NV * rsz : 0;
   L.g = diff ? NV * rsz : 0;
   L.ier = (diff && has_aux) ? NB * 8 : 0;
-  L.locp = (size_t)G.n_loc * 8;
+  L.locp = (size_t)2 * G.n_loc * 8;
   L.gR = (size_t)n_sets * K * kSlots * 8;
   L.gS = (size_t)n_sets * G.n_age * kSlots * 8;
   L.gi0 = (size_t)n_sets * kSlots * 8;
@@ -362,10 +362,15 @@ static void loc_pass(Sim& s, const V& val, double* acc, hipStream_t st) {
   L.lv_agent = G.lv_agent; L.lv_loc = G.lv_loc; L.lv_w = G.lv_w;
   L.av_ptr = G.av_ptr; L.av_loc = G.av_loc; L.av_w = G.av_w;
   KTime kt(s, st, GABM_KT_LOC);
-  fill0(s.loc_P, (size_t)G.n_loc * 8, st);
-  hipLaunchKernelGGL(k_loc_pressure<V>, dim3(blocks_capped(G.n_visits)), dim3(kBlock), 0, st, L, val, s.loc_P);
-  hipLaunchKernelGGL(k_loc_gather<V>, dim3(blocks_capped(G.N)), dim3(kBlock), 0, st, L, val, (const double*)s.loc_P,
-                     acc);
+  // the pass's buffer was cleared by the previous pass (or by b1_init); this
+  // pass clears the other one.  The sequence of passes of a run is fixed, so
+  // a captured run replays the same buffer order.
+  double* P = s.loc_P + (size_t)s.loc_par * G.n_loc;
+  double* Pn = s.loc_P + (size_t)(1 - s.loc_par) * G.n_loc;
+  hipLaunchKernelGGL(k_loc_pressure<V>, dim3(blocks_capped(G.n_visits)), dim3(kBlock), 0, st, L, val, P);
+  hipLaunchKernelGGL(k_loc_gather<V>, dim3(blocks_capped(std::max<int64_t>(G.N, G.n_loc))), dim3(kBlock), 0, st, L,
+                     val, (const double*)P, acc, Pn);
+  s.loc_par = 1 - s.loc_par;
 }
 
 template <typename RT>
@@ -374,6 +379,9 @@ static void b1_init(Sim& s, const DParams& P, Rng rng, uint32_t stream, hipStrea
   const bool soft = s.mode == GABM_SOFT;
   // the daily-layer accumulator is cleared by each day's consumer; start clean
   fill0(s.A_er, s.A_er ? (size_t)s.NB * 8 : 0, st);
+  // both pressure buffers of the location layer
+  fill0(s.loc_P, s.loc_P ? (size_t)2 * G.n_loc * 8 : 0, st);
+  s.loc_par = 0;
   // neighbour sums of the split path: rows without contacts are never written
   fill0(s.Abuf, s.Abuf ? (size_t)G.n_slices * G.N * 8 : 0, st);
   if (!soft)
@@ -463,12 +471,15 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
       hipLaunchKernelGGL(k_gather_fast<false>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
     }
     KTime kt(s, st, GABM_KT_AGENT_FWD);
-    if (G.n_pops > 1)
-      hipLaunchKernelGGL(k_agent_fwd<true>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a,
-                         slice_sums(ga));
-    else
-      hipLaunchKernelGGL(k_agent_fwd<false>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(FwdArgs<float>*)&a,
-                         slice_sums(ga));
+    const FwdArgs<float>& af = *(FwdArgs<float>*)&a;
+    const dim3 grid(blocks_for(G.N)), blk(kBlock);
+    if (P.dwell_E) {
+      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_fwd<true, true>), grid, blk, 0, st, af, slice_sums(ga));
+      else hipLaunchKernelGGL((k_agent_fwd<false, true>), grid, blk, 0, st, af, slice_sums(ga));
+    } else {
+      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_fwd<true, false>), grid, blk, 0, st, af, slice_sums(ga));
+      else hipLaunchKernelGGL((k_agent_fwd<false, false>), grid, blk, 0, st, af, slice_sums(ga));
+    }
   } else {
     KTime kt(s, st, GABM_KT_DAY_FWD);
     if (soft) hipLaunchKernelGGL((k_day_fwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
@@ -565,12 +576,15 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
       hipLaunchKernelGGL(k_gather_fast<true>, dim3(s.n_cu), dim3(kFastBlock), 0, st, ga);
     }
     KTime kt(s, st, GABM_KT_AGENT_BWD);
-    if (G.n_pops > 1)
-      hipLaunchKernelGGL(k_agent_bwd<true>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm,
-                         slice_sums(ga));
-    else
-      hipLaunchKernelGGL(k_agent_bwd<false>, dim3(blocks_for(G.N)), dim3(kBlock), 0, st, *(BwdArgs<float>*)&a, fm,
-                         slice_sums(ga));
+    const BwdArgs<float>& ab = *(BwdArgs<float>*)&a;
+    const dim3 grid(blocks_for(G.N)), blk(kBlock);
+    if (P.dwell_E) {
+      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_bwd<true, true>), grid, blk, 0, st, ab, fm, slice_sums(ga));
+      else hipLaunchKernelGGL((k_agent_bwd<false, true>), grid, blk, 0, st, ab, fm, slice_sums(ga));
+    } else {
+      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_bwd<true, false>), grid, blk, 0, st, ab, fm, slice_sums(ga));
+      else hipLaunchKernelGGL((k_agent_bwd<false, false>), grid, blk, 0, st, ab, fm, slice_sums(ga));
+    }
   } else {
     KTime kt(s, st, GABM_KT_DAY_BWD);
     if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
@@ -713,6 +727,10 @@ static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st
   fill0(s.ring, (size_t)s.W * s.NV * s.rsz, st);
   fill0(s.Sbar, s.NV * s.rsz, st);
   fill0(s.infbar_er, s.infbar_er ? (size_t)s.NB * 8 : 0, st);
+  // every run-level pass sequence starts from clear pressure buffers at parity
+  // 0, whatever earlier (possibly replayed) sequences left in the host state
+  fill0(s.loc_P, s.loc_P ? (size_t)2 * s.G->n_loc * 8 : 0, st);
+  s.loc_par = 0;
   for (int k = 0; k < 3; ++k) fill0(s.gz[k], s.gz_bytes, st);
   if (s.wq) fill0(s.wq + s.K, (size_t)(2 * s.K + 1) * 4, st);  // counters of replayed days and reverse steps
   fill0(s.gR, (size_t)s.n_sets * s.K * kSlots * 8, st);

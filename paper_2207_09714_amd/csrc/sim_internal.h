@@ -53,7 +53,8 @@ struct Sim {
   void* Sbar = nullptr;  // [NB]
   void* g[2] = {nullptr, nullptr};
   double* infbar_er = nullptr;  // [NB]
-  double* loc_P = nullptr;      // [n_locations] location pressures of the current pass
+  double* loc_P = nullptr;      // [2][n_locations] location pressures; passes alternate buffers
+  int loc_par = 0;              // buffer of the next pass (zero on entry)
   double* gR = nullptr;   // [n_sets][K][kSlots]
   double* gS = nullptr;   // [n_sets][n_age][kSlots]
   double* gi0 = nullptr;  // [n_sets][kSlots]

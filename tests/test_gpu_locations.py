@@ -291,3 +291,31 @@ def test_location_layer_hip_graph_replays_and_timing(G):
     for c, gv in res[True]:
         assert np.array_equal(c, c0)
         assert np.allclose(gv, g0, rtol=1e-9)
+
+
+def test_location_layer_day_level_entry_points_after_replays(G):
+    """The per-day entry points on a location graph, run after captured runs
+    have been replayed on the same simulation (the pressure buffers must start
+    clear whatever the replays left), equal the whole run."""
+    wl = make_workload("c2", n_agents=6000, K=15)
+    visits, nl, Z = with_visits(wl)
+    _say(f"location layer, day-level entry points after replays N={wl.n_agents}")
+    g = graph_of(G, wl, visits, nl)
+    t = torch.tensor(np.linspace(0.0, 0.5, wl.K), device="cuda")
+    eager = G.Simulator(g, K=wl.K, Z=Z, mode=G.HARD_ST, ckpt_every=0, tau_g=wl.tau_g)
+    pe = eager.params(wl.R, wl.S, wl.m, wl.i0)
+    out = eager.forward(pe, seed=wl.seed, target=t)
+    want_c = out["counts"].cpu().numpy().copy()
+    want_g = grads_vec(eager.backward(pe, seed=wl.seed))
+    sim = G.Simulator(g, K=wl.K, Z=Z, mode=G.HARD_ST, ckpt_every=0, tau_g=wl.tau_g, use_hip_graph=True)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    for _ in range(2):
+        sim.forward(pb, seed=wl.seed, target=t)
+        sim.backward(pb, seed=wl.seed)
+    sim.forward(pb, seed=wl.seed, target=t)  # replayed forward, then the reverse day by day
+    for d in range(wl.K, -1, -1):
+        sim.day_bwd(pb, d, seed=wl.seed)
+    assert np.allclose(grads_vec({"dR": sim.dR, "dS": sim.dS, "dm": sim.dm, "di0": sim.di0}), want_g, rtol=1e-9)
+    for d in range(wl.K):
+        sim.day_fwd(pb, d, seed=wl.seed, target=t)
+    assert np.array_equal(sim.counts.cpu().numpy(), want_c)
