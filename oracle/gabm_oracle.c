@@ -430,13 +430,15 @@ int ora_run(const ora_cfg *c, ora_out *o) {
       }
       ws.Sv[i] = Sv - xi;
       ws.xi[slot] = xi; /* overwrites xi^{t-W}, already used above */
-      /* the lengths an exposure of agent i on day t takes (drawn whether or not it happens) */
-      ws.dE[slot] = (uint8_t)(dwell ? ora_dwell_draw(c->dwell_E, tE, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
-                                                    ORA_TAG_DWELL_E, pid, c->stream)
-                                    : tE);
-      ws.dI[slot] = (uint8_t)(dwell ? ora_dwell_draw(c->dwell_I, tI, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
-                                                    ORA_TAG_DWELL_I, pid, c->stream)
-                                    : tI);
+      /* the lengths an exposure of agent i on day t takes; they only weigh
+       * exposure mass or its tangents, so without either any value serves */
+      const int draw_now = dwell && (xi != 0.0 || nd > 0);
+      ws.dE[slot] = (uint8_t)(draw_now ? ora_dwell_draw(c->dwell_E, tE, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
+                                                       ORA_TAG_DWELL_E, pid, c->stream)
+                                       : tE);
+      ws.dI[slot] = (uint8_t)(draw_now ? ora_dwell_draw(c->dwell_I, tI, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
+                                                       ORA_TAG_DWELL_I, pid, c->stream)
+                                       : tI);
 
       /* ---- Progress (hard stage machine) ---- */
       if (mode != ORA_SOFT) {
