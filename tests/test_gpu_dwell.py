@@ -171,3 +171,25 @@ def test_dwell_argument_checks(G):
     with pytest.raises(L.GabmError) as e:
         G.Simulator(gb, n_sets=2, K=wb.K, Z=wb.Z, mode=G.HARD_ST, tau_g=wb.tau_g, dwell=DWELL)
     assert e.value.code == L.EUNSUPPORTED
+
+
+@pytest.mark.timeout(300)
+def test_full_size_c3_with_dwell(G, O):
+    """The 1M-agent, 90-day workload with drawn dwell times in the benchmark's
+    launch configuration (split kernels, float32 state, straight-through mode,
+    checkpoint every 10 days): daily counts, removals and every agent's final
+    stage equal the oracle's."""
+    wl = make_workload("c3")
+    _say(f"full c3 with dwell tables N={wl.n_agents} E={wl.n_edges} K={wl.K}")
+    g = G.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age)
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.HARD_ST, ckpt_every=10, tau_g=wl.tau_g, dwell=DWELL)
+    out = sim.forward(sim.params(wl.R, wl.S, wl.m, wl.i0), seed=wl.seed)
+    counts = out["counts"][0].cpu().numpy()
+    drm = out["drm"][0].cpu().numpy()
+    last = (sim.records().cpu().numpy().view(np.uint32) & 0xFF).astype(np.uint8)
+    del sim, g
+    ref = O.run_workload(wl, mode=O.PLAIN, want_stage=True, dwell=DWELL)
+    assert ref["mismatch"] == 0
+    assert np.array_equal(counts, ref["counts"])
+    assert np.array_equal(drm, ref["drm"])
+    assert np.array_equal(last, ref["stage"][-1])

@@ -319,3 +319,27 @@ def test_location_layer_day_level_entry_points_after_replays(G):
     for d in range(wl.K):
         sim.day_fwd(pb, d, seed=wl.seed, target=t)
     assert np.array_equal(sim.counts.cpu().numpy(), want_c)
+
+
+@pytest.mark.timeout(300)
+def test_full_size_c3_with_venues(G, O):
+    """The 1M-agent, 90-day workload plus the JUNE-like venues of the
+    benchmark's location leg (1.1M visits), in its launch configuration
+    (split kernels, float32 state, straight-through mode, checkpoint every 10
+    days): daily counts and removals equal the oracle's."""
+    wl = make_workload("c3")
+    va, vl, vw, nl = location_visits(wl.pop, np.random.default_rng(0x10C))
+    deg = location_degree(wl.n_agents, (va, vl, vw))
+    Z = (wl.Z + np.float32(wl.tau_I * deg.mean())).astype(np.float32)
+    _say(f"full c3 with venues N={wl.n_agents} E={wl.n_edges} V={len(va)} L={nl} K={wl.K}")
+    g = G.Graph(n_agents=wl.n_agents, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, visits=(va, vl, vw),
+                n_locations=nl)
+    sim = G.Simulator(g, K=wl.K, Z=Z, mode=G.HARD_ST, ckpt_every=10, tau_g=wl.tau_g)
+    out = sim.forward(sim.params(wl.R, wl.S, wl.m, wl.i0), seed=wl.seed)
+    counts = out["counts"][0].cpu().numpy()
+    drm = out["drm"][0].cpu().numpy()
+    del sim, g
+    ref = O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=wl.R[0],
+                S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=Z, T=wl.T, mode=O.PLAIN, seed=wl.seed, visits=(va, vl, vw))
+    assert np.array_equal(counts, ref["counts"])
+    assert np.array_equal(drm, ref["drm"])
