@@ -90,6 +90,56 @@ int32_t ora_dwell_draw(const float *lw, int32_t n, uint64_t seed, uint32_t idx, 
   return best + 1;
 }
 
+/* The relaxed one-hot of the same draw: ch = softmax((lw + G) / tau). */
+static void dwell_relaxed(const float *lw, int32_t n, double tau, uint64_t seed, uint32_t idx, uint32_t day,
+                          uint32_t tag0, uint32_t pop, uint32_t stream, double *ch) {
+  uint32_t o[4];
+  double mx = -INFINITY, sum = 0.0;
+  for (int32_t k = 0; k < n; ++k) {
+    if (k % 4 == 0) draw(seed, idx, day, tag0 + (uint32_t)(k / 4), pop, stream, o);
+    ch[k] = ((double)lw[k] - log(-log(to_unit(o[k % 4])))) / tau;
+    if (ch[k] > mx) mx = ch[k];
+  }
+  for (int32_t k = 0; k < n; ++k) {
+    ch[k] = exp(ch[k] - mx);
+    sum += ch[k];
+  }
+  for (int32_t k = 0; k < n; ++k) ch[k] /= sum;
+}
+
+/* Weights of an exposure k days back of being E, being I, and leaving I on
+ * that day, for length weights cE over 1..tE and cI over 1..tI (one-hots of
+ * drawn lengths, relaxed one-hots, or their tangents): E while k <= a; I
+ * while a < k <= a + b; leaving on k = a + b. */
+static void win_w(const double *cE, int32_t tE, const double *cI, int32_t tI, int32_t k, double *wE, double *wI,
+                  double *wR) {
+  double e = 0.0, i = 0.0, r = 0.0;
+  for (int32_t a = 1; a <= tE; ++a) {
+    double ca = cE[a - 1];
+    if (ca == 0.0) continue;
+    if (k <= a) {
+      e += ca;
+      continue;
+    }
+    int32_t m = k - a; /* the k-th day is day m of I */
+    if (m > tI) continue;
+    double tail = 0.0;
+    for (int32_t b = m; b <= tI; ++b) tail += cI[b - 1];
+    i += ca * tail;
+    r += ca * cI[m - 1];
+  }
+  *wE = e;
+  *wI = i;
+  *wR = r;
+}
+
+/* dc = c * (dlw - <c, dlw>) / tau, the tangent of a relaxed one-hot */
+static void relaxed_tangent(const double *c, const double *dlw, int32_t n, double tau, double *dc) {
+  double m = 0.0;
+  for (int32_t k = 0; k < n; ++k) m += c[k] * dlw[k];
+  for (int32_t k = 0; k < n; ++k) dc[k] = c[k] * (dlw[k] - m) / tau;
+}
+
 /* Daily random-contact layer: G(n, M) with M = round(n*mean/2) undirected
  * pairs, endpoints from words 0 and 1 by exact 32x32->64 multiplication. */
 int64_t ora_er_pairs(int32_t n_pop, double mean_deg, uint64_t seed, uint32_t day, uint32_t pop,
@@ -153,6 +203,8 @@ typedef struct {
   uint8_t *stage, *timer;
   uint8_t *dE, *dI;  /* [W*n] dwell lengths of an exposure on day u, at slot u mod W */
   uint8_t *dI0;      /* [n] I length of an initial infection */
+  double *cE, *cI;   /* [W*n*8] relaxed one-hots of each slot's draws (with relaxed dwell or dwell tangents) */
+  double *cI0;       /* [n*8] the same for the initial infections' I length */
   int32_t *eday;     /* [n] exposure day of the hard state */
   int32_t *pop_of, *local;
   int32_t *er_a, *er_b;
@@ -161,8 +213,39 @@ typedef struct {
 static void ws_free(ws_t *w) {
   free(w->xi); free(w->dxi); free(w->Sv); free(w->dSv); free(w->x0); free(w->dx0);
   free(w->inf); free(w->dinf); free(w->A); free(w->dA); free(w->stage); free(w->timer);
-  free(w->dE); free(w->dI); free(w->dI0); free(w->eday);
+  free(w->dE); free(w->dI); free(w->dI0); free(w->eday); free(w->cE); free(w->cI); free(w->cI0);
   free(w->pop_of); free(w->local); free(w->er_a); free(w->er_b);
+}
+
+/* Tangent of the window weights of ring slot sl (k days back) along
+ * direction d of the dwell log weights: bilinear in (c_E, c_I), with c the
+ * relaxed one-hots (rel_fwd) or the one-hots of the drawn lengths. */
+static void dwell_dw(const ws_t *ws, const ora_cfg *c, int rel_fwd, size_t sl, int32_t d, int32_t k, double tau,
+                     double *dwE, double *dwI, double *dwR) {
+  const int32_t tE = c->tau_E, tI = c->tau_I;
+  double cE[8], cI[8], dcE[8], dcI[8], zE[8] = {0}, zI[8] = {0};
+  for (int32_t a = 0; a < tE; ++a) cE[a] = rel_fwd ? ws->cE[sl * 8 + a] : (a + 1 == ws->dE[sl] ? 1.0 : 0.0);
+  for (int32_t b = 0; b < tI; ++b) cI[b] = rel_fwd ? ws->cI[sl * 8 + b] : (b + 1 == ws->dI[sl] ? 1.0 : 0.0);
+  relaxed_tangent(ws->cE + sl * 8, c->ddwE ? c->ddwE + (size_t)d * tE : zE, tE, tau, dcE);
+  relaxed_tangent(ws->cI + sl * 8, c->ddwI ? c->ddwI + (size_t)d * tI : zI, tI, tau, dcI);
+  double e1, i1, r1, e2, i2, r2;
+  win_w(dcE, tE, cI, tI, k, &e1, &i1, &r1);
+  win_w(cE, tE, dcI, tI, k, &e2, &i2, &r2);
+  *dwE = e1;
+  *dwI = i1 + i2;
+  *dwR = r1 + r2;
+}
+
+/* the same for an initial infection on day t (only an I length): I weight and leaving weight */
+static void init_dw(const ws_t *ws, const ora_cfg *c, int32_t j, int32_t d, int32_t t, double tau, double *dwI,
+                    double *dwR) {
+  const int32_t tI = c->tau_I;
+  double dcI[8], zI[8] = {0};
+  relaxed_tangent(ws->cI0 + (size_t)j * 8, c->ddwI ? c->ddwI + (size_t)d * tI : zI, tI, tau, dcI);
+  double s = 0.0;
+  for (int32_t b = t + 1; b <= tI; ++b) s += dcI[b - 1];
+  *dwI = s;
+  *dwR = (t + 1 <= tI && t >= 0) ? dcI[t] : 0.0;
 }
 
 /* accumulate A_i = sum over contacts j->i of w * v_j (static layers in the
@@ -210,11 +293,42 @@ int ora_run(const ora_cfg *c, ora_out *o) {
   if (c->pop_offsets[0] != 0 || c->pop_offsets[c->n_pops] != n) return -6;
   const int dwell = c->dwell_E != NULL || c->dwell_I != NULL;
   if (dwell && (!c->dwell_E || !c->dwell_I || tE > 8 || tI > 8 || c->iota)) return -8;
+  /* dwell tangents; relaxed windows in the forward (SOFT); either needs the relaxed one-hots */
+  const int ddw = dwell && nd > 0 && (c->ddwE || c->ddwI);
+  const int rel_fwd = dwell && mode == ORA_SOFT;
+  const int rel = ddw || rel_fwd;
+  if ((c->ddwE || c->ddwI) && (!dwell || mode == ORA_PLAIN)) return -9;
 
   const double TE = c->T[ORA_E], TI = c->T[ORA_I];
   const double m = c->m, i0 = c->i0, tau = c->tau_g;
   /* weight of the k-th day after exposure (k = 1..W): the profile value, 1 when flat */
 #define IOTA(k) (c->iota ? (double)c->iota[(k) - 1] : 1.0)
+  /* E, I and leaving weights of ring slot sl, k days back: the relaxed
+   * mixture in SOFT mode with dwell tables, else the drawn (or fixed) lengths */
+#define SLOT_W(sl, k, eW, iW, rW)                                                           \
+  do {                                                                                      \
+    if (rel_fwd) {                                                                          \
+      win_w(ws.cE + (sl) * 8, tE, ws.cI + (sl) * 8, tI, (k), &(eW), &(iW), &(rW));          \
+    } else {                                                                                \
+      int32_t a_ = ws.dE[sl], b_ = ws.dI[sl];                                               \
+      eW = (k) <= a_ ? 1.0 : 0.0;                                                           \
+      iW = ((k) > a_ && (k) <= a_ + b_) ? 1.0 : 0.0;                                        \
+      rW = (k) == a_ + b_ ? 1.0 : 0.0;                                                      \
+    }                                                                                       \
+  } while (0)
+  /* an initial infection on day tt: I weight and leaving weight */
+#define INIT_W(j, tt, iW, rW)                                                               \
+  do {                                                                                      \
+    if (rel_fwd) {                                                                          \
+      double s_ = 0.0;                                                                      \
+      for (int32_t b_ = (tt) + 1; b_ <= tI; ++b_) s_ += ws.cI0[(size_t)(j) * 8 + b_ - 1];   \
+      iW = s_;                                                                              \
+      rW = ((tt) + 1 <= tI) ? ws.cI0[(size_t)(j) * 8 + (tt)] : 0.0;                         \
+    } else {                                                                                \
+      iW = (tt) < ws.dI0[j] ? 1.0 : 0.0;                                                    \
+      rW = (tt) == ws.dI0[j] - 1 ? 1.0 : 0.0;                                               \
+    }                                                                                       \
+  } while (0)
 
   ws_t ws;
   memset(&ws, 0, sizeof ws);
@@ -230,6 +344,15 @@ int ora_run(const ora_cfg *c, ora_out *o) {
   ws.dI = calloc((size_t)W * n, 1);
   ws.dI0 = calloc(n, 1);
   ws.eday = calloc(n, sizeof(int32_t));
+  if (rel) {
+    ws.cE = calloc((size_t)W * n * 8, sizeof(double));
+    ws.cI = calloc((size_t)W * n * 8, sizeof(double));
+    ws.cI0 = calloc((size_t)n * 8, sizeof(double));
+    if (!ws.cE || !ws.cI || !ws.cI0) {
+      ws_free(&ws);
+      return -7;
+    }
+  }
   ws.pop_of = calloc(n, sizeof(int32_t));
   ws.local = calloc(n, sizeof(int32_t));
   int64_t er_cap = 16;
@@ -271,6 +394,9 @@ int ora_run(const ora_cfg *c, ora_out *o) {
     ws.dI0[i] = (uint8_t)(dwell ? ora_dwell_draw(c->dwell_I, tI, c->seed, (uint32_t)ws.local[i], 0xFFFFFFFFu,
                                                  ORA_TAG_DWELL_I, pid, c->stream)
                                 : tI);
+    if (rel)
+      dwell_relaxed(c->dwell_I, tI, tau, c->seed, (uint32_t)ws.local[i], 0xFFFFFFFFu, ORA_TAG_DWELL_I, pid, c->stream,
+                    ws.cI0 + (size_t)i * 8);
     ws.stage[i] = hard ? ORA_I : ORA_S;
     ws.timer[i] = hard ? ws.dI0[i] : 0;
     double y0 = 0.0, dy0 = 0.0;
@@ -305,11 +431,17 @@ int ora_run(const ora_cfg *c, ora_out *o) {
           int32_t u_ = (tt) - k_;                                                           \
           if (u_ < 0) break;                                                                \
           size_t sl_ = (size_t)(u_ % W) * n + i_;                                           \
-          if (k_ > ws.dE[sl_] + ws.dI[sl_]) continue;                                       \
+          double eW_, iW_, rW_;                                                             \
+          SLOT_W(sl_, k_, eW_, iW_, rW_);                                                   \
+          if (eW_ == 0.0 && iW_ == 0.0) continue;                                           \
           double xv = ws.xi[sl_];                                                           \
-          if (k_ <= ws.dE[sl_]) sE += xv; else sI += xv;                                    \
+          sE += eW_ * xv;                                                                   \
+          sI += iW_ * xv;                                                                   \
         }                                                                                   \
-        if ((tt) < ws.dI0[i_]) sI += ws.x0[i_];                                             \
+        double i0W_, r0W_;                                                                  \
+        INIT_W(i_, (tt), i0W_, r0W_);                                                       \
+        (void)r0W_;                                                                         \
+        if (i0W_ != 0.0) sI += i0W_ * ws.x0[i_];                                            \
       }                                                                                     \
       double rm = (double)n - sS - sE - sI;                                                 \
       cc[ORA_S] = sS; cc[ORA_E] = sE; cc[ORA_I] = sI;                                       \
@@ -331,11 +463,18 @@ int ora_run(const ora_cfg *c, ora_out *o) {
         int32_t u = t - k;
         if (u < 0) break;
         size_t sl = (size_t)(u % W) * n + j;
-        if (k > ws.dE[sl] + ws.dI[sl]) continue; /* that exposure has left I */
+        double eW, iW, rW;
+        SLOT_W(sl, k, eW, iW, rW);
+        if (eW == 0.0 && iW == 0.0) continue; /* that exposure has left I */
         double xv = ws.xi[sl];
-        if (k <= ws.dE[sl]) { wE += xv; pE += IOTA(k) * xv; } else { wI += xv; pI += IOTA(k) * xv; }
+        wE += eW * xv;
+        pE += IOTA(k) * (eW * xv);
+        wI += iW * xv;
+        pI += IOTA(k) * (iW * xv);
       }
-      if (t < ws.dI0[j]) { wI += ws.x0[j]; pI += IOTA(t + tE + 1) * ws.x0[j]; }
+      double i0W, r0W;
+      INIT_W(j, t, i0W, r0W);
+      if (i0W != 0.0) { wI += i0W * ws.x0[j]; pI += IOTA(t + tE + 1) * (i0W * ws.x0[j]); }
       double win = TE * wE + TI * wI;
       double pwin = TE * pE + TI * pI;
       if (mode == ORA_SOFT) {
@@ -353,11 +492,26 @@ int ora_run(const ora_cfg *c, ora_out *o) {
           int32_t u = t - k;
           if (u < 0) break;
           size_t sl = (size_t)(u % W) * n + j;
-          if (k > ws.dE[sl] + ws.dI[sl]) continue;
-          double xv = IOTA(k) * dx[sl];
-          if (k <= ws.dE[sl]) dE += xv; else dI += xv;
+          double eW, iW, rW;
+          SLOT_W(sl, k, eW, iW, rW);
+          if (eW != 0.0 || iW != 0.0) {
+            double xv = IOTA(k) * dx[sl];
+            dE += eW * xv;
+            dI += iW * xv;
+          }
+          if (ddw && ws.xi[sl] != 0.0) { /* the windows' own tangent along the dwell log weights */
+            double a, b, r;
+            dwell_dw(&ws, c, rel_fwd, sl, d, k, tau, &a, &b, &r);
+            dE += a * ws.xi[sl];
+            dI += b * ws.xi[sl];
+          }
         }
-        if (t < ws.dI0[j]) dI += IOTA(t + tE + 1) * ws.dx0[(size_t)d * n + j];
+        if (i0W != 0.0) dI += IOTA(t + tE + 1) * (i0W * ws.dx0[(size_t)d * n + j]);
+        if (ddw && ws.x0[j] != 0.0) {
+          double a, r;
+          init_dw(&ws, c, j, d, t, tau, &a, &r);
+          dI += a * ws.x0[j];
+        }
         ws.dinf[(size_t)d * n + j] = TE * dE + TI * dI;
       }
     }
@@ -375,14 +529,31 @@ int ora_run(const ora_cfg *c, ora_out *o) {
       for (int32_t i = 0; i < n; ++i) {
         for (int32_t k = 1; k <= W && t - k >= 0; ++k) {
           size_t sl = (size_t)((t - k) % W) * n + i;
-          if (ws.dE[sl] + ws.dI[sl] != k) continue;
-          drm_w += ws.xi[sl];
-          for (int32_t d = 0; d < nd; ++d) drm_dir[d] += ws.dxi[(size_t)d * W * n + sl];
+          double eW, iW, rW;
+          SLOT_W(sl, k, eW, iW, rW);
+          if (rW != 0.0) {
+            drm_w += rW * ws.xi[sl];
+            for (int32_t d = 0; d < nd; ++d) drm_dir[d] += rW * ws.dxi[(size_t)d * W * n + sl];
+          }
+          if (ddw && ws.xi[sl] != 0.0)
+            for (int32_t d = 0; d < nd; ++d) {
+              double a, b, r;
+              dwell_dw(&ws, c, rel_fwd, sl, d, k, tau, &a, &b, &r);
+              drm_dir[d] += r * ws.xi[sl];
+            }
         }
-        if (t == ws.dI0[i] - 1) {
-          drm_w += ws.x0[i];
-          for (int32_t d = 0; d < nd; ++d) drm_dir[d] += ws.dx0[(size_t)d * n + i];
+        double i0W, r0W;
+        INIT_W(i, t, i0W, r0W);
+        if (r0W != 0.0) {
+          drm_w += r0W * ws.x0[i];
+          for (int32_t d = 0; d < nd; ++d) drm_dir[d] += r0W * ws.dx0[(size_t)d * n + i];
         }
+        if (ddw && ws.x0[i] != 0.0)
+          for (int32_t d = 0; d < nd; ++d) {
+            double a, r;
+            init_dw(&ws, c, i, d, t, tau, &a, &r);
+            drm_dir[d] += r * ws.x0[i];
+          }
       }
     } else {
       int32_t u = t - W;
@@ -439,6 +610,12 @@ int ora_run(const ora_cfg *c, ora_out *o) {
       ws.dI[slot] = (uint8_t)(draw_now ? ora_dwell_draw(c->dwell_I, tI, c->seed, (uint32_t)ws.local[i], (uint32_t)t,
                                                        ORA_TAG_DWELL_I, pid, c->stream)
                                        : tI);
+      if (rel && draw_now) {
+        dwell_relaxed(c->dwell_E, tE, tau, c->seed, (uint32_t)ws.local[i], (uint32_t)t, ORA_TAG_DWELL_E, pid,
+                      c->stream, ws.cE + slot * 8);
+        dwell_relaxed(c->dwell_I, tI, tau, c->seed, (uint32_t)ws.local[i], (uint32_t)t, ORA_TAG_DWELL_I, pid,
+                      c->stream, ws.cI + slot * 8);
+      }
 
       /* ---- Progress (hard stage machine) ---- */
       if (mode != ORA_SOFT) {
@@ -478,6 +655,8 @@ int ora_run(const ora_cfg *c, ora_out *o) {
     SNAPSHOT(t + 1);
   }
 #undef SNAPSHOT
+#undef SLOT_W
+#undef INIT_W
 #undef IOTA
   *o->loss = loss / (double)K;
   if (o->mismatch) *o->mismatch = mismatch;

@@ -83,6 +83,14 @@ typedef struct {
    * uniforms of (i, u); an initial infection's I length uses day 2^32 - 1.
    * Not combined with an infectiousness profile. */
   const float *dwell_E, *dwell_I;
+  /* tangent directions of the dwell log weights, [ndir*tau_E] and
+   * [ndir*tau_I], or NULL (zero).  The drawn lengths get the straight-through
+   * Gumbel-softmax rule (Jang, Gu & Poole 2017): the forward keeps the drawn
+   * one-hot c, the tangent is that of the relaxed one-hot
+   * softmax((lw + G) / tau_g) with the same Gumbel noise G, and the window
+   * weights are bilinear in (c_E, c_I).  In SOFT mode the relaxed one-hots
+   * replace the drawn lengths in the forward as well (a mixture of windows). */
+  const double *ddwE, *ddwI;
 } ora_cfg;
 
 typedef struct {

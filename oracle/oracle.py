@@ -42,6 +42,7 @@ class _Cfg(C.Structure):
         ("iota", C.c_void_p),
         ("n_locations", C.c_int32), ("n_visits", C.c_int64), ("visit_agent", C.c_void_p), ("visit_loc", C.c_void_p),
         ("visit_w", C.c_void_p), ("loc_p", C.c_void_p), ("dwell_E", C.c_void_p), ("dwell_I", C.c_void_p),
+        ("ddwE", C.c_void_p), ("ddwI", C.c_void_p),
     ]
 
 
@@ -120,6 +121,22 @@ def standard_directions(K: int, n_age: int):
     return dR, dS, dm, di0
 
 
+def dwell_directions(K: int, n_age: int, tau_E: int, tau_I: int):
+    """standard_directions followed by one unit direction per dwell log
+    weight (E lengths 1..tau_E, then I lengths 1..tau_I), as six arrays."""
+    dR, dS, dm, di0 = standard_directions(K, n_age)
+    n0 = dR.shape[0]
+    nd = n0 + tau_E + tau_I
+    pad = lambda x: np.concatenate([x, np.zeros((nd - n0,) + x.shape[1:])])  # noqa: E731
+    ddE = np.zeros((nd, tau_E))
+    ddI = np.zeros((nd, tau_I))
+    for a in range(tau_E):
+        ddE[n0 + a, a] = 1.0
+    for b in range(tau_I):
+        ddI[n0 + tau_E + b, b] = 1.0
+    return pad(dR), pad(dS), pad(dm), pad(di0), ddE, ddI
+
+
 def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), tau_E=3, tau_I=5,
         mode=PLAIN, tau_g=0.5, seed=0, stream=0, pop_id_base=0, er_mean_deg=0.0, er_weight=0.0,
         target=None, directions=None, want_agents=False, want_stage=False, iota=None, visits=None, dwell=None):
@@ -137,7 +154,9 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
     1..tau_I) for stochastic dwell times drawn per exposure by Gumbel-max, or
     None for the fixed tau_E / tau_I.
 
-    ``directions`` = (dR[nd,K], dS[nd,n_age], dm[nd], di0[nd]) or None.
+    ``directions`` = (dR[nd,K], dS[nd,n_age], dm[nd], di0[nd]) or None, with
+    optionally two more, (ddw_E[nd,tau_E], ddw_I[nd,tau_I]), the directions of
+    the dwell log weights (straight-through Gumbel-softmax tangents).
     Returns a dict with counts [K+1,5], drm [K], deaths [K], loss, and when
     requested per-agent arrays [K,N] (A, lam, y, h), stage [K+1,N], dL [nd],
     dD [nd,K], mismatch.
@@ -186,10 +205,14 @@ def run(*, age, pop_offsets, src, dst, w, K, R, S, m, i0, Z, T=(0, 0, 1, 0, 0), 
         keep += [dE, dI]
     nd = 0
     if directions is not None:
-        dR, dS, dm, di0 = (np.ascontiguousarray(x, np.float64) for x in directions)
+        dR, dS, dm, di0 = (np.ascontiguousarray(x, np.float64) for x in directions[:4])
         nd = dR.shape[0]
         cfg.ndir, cfg.dR, cfg.dS, cfg.dm, cfg.di0 = nd, _p(dR), _p(dS), _p(dm), _p(di0)
         keep += [dR, dS, dm, di0]
+        if len(directions) > 4:  # tangents of the dwell log weights
+            ddE, ddI = (np.ascontiguousarray(x, np.float64) for x in directions[4:6])
+            cfg.ddwE, cfg.ddwI = _p(ddE), _p(ddI)
+            keep += [ddE, ddI]
     res = {
         "counts": np.zeros((K + 1, 5)), "drm": np.zeros(K), "deaths": np.zeros(K), "loss": np.zeros(1),
         "mismatch": np.zeros(1, np.int64),

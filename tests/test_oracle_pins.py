@@ -631,3 +631,64 @@ def test_dwell_tables_are_checked():
         O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=2.5,
               S=wl.S[0], m=0.01, i0=0.01, Z=wl.Z, tau_E=9, tau_I=5,
               dwell=(np.zeros(9, np.float32), np.zeros(5, np.float32)))
+
+
+def test_soft_dwell_weight_tangents_match_finite_differences():
+    """Relaxed mode with dwell tables: the relaxed one-hots of the Gumbel-max
+    draws weight a mixture of windows, so the loss is smooth in the log weights
+    and the tangents along each of them equal central differences."""
+    wl, tgt = _soft_setup()
+    K = wl.K
+    dirs = O.dwell_directions(K, 8, 3, 5)
+    r = O.run_workload(wl, mode=O.SOFT, target=tgt, directions=dirs, dwell=DWELL)
+    g = r["dL"][11:]
+    assert np.all(np.isfinite(g)) and np.max(np.abs(g)) > 0
+
+    def loss_at(which, k, delta):
+        lw = [DWELL[0].copy(), DWELL[1].copy()]
+        lw[which][k] = np.float32(lw[which][k] + delta)
+        return O.run_workload(wl, mode=O.SOFT, target=tgt, dwell=tuple(lw))["loss"]
+
+    h = 2.0**-8
+    gmax = np.max(np.abs(g))
+    for idx in range(8):
+        which, k = (0, idx) if idx < 3 else (1, idx - 3)
+        d1 = (loss_at(which, k, h) - loss_at(which, k, -h)) / (2 * h)
+        d2 = (loss_at(which, k, h / 2) - loss_at(which, k, -h / 2)) / h
+        fd = (4 * d2 - d1) / 3
+        assert abs(fd - g[idx]) <= 1e-6 * max(abs(g[idx]), 1e-3 * gmax), (idx, fd, g[idx])
+
+
+def _relaxed_one_hot(lw, seed, idx, day, tag0, tau):
+    """Gumbel noise of the (idx, day) counter, re-derived from Philox words:
+    the drawn length and softmax((lw + G) / tau)."""
+    G = []
+    for k in range(len(lw)):
+        o = O.philox([idx, day, tag0 + k // 4, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        u = (2 * (int(o[k % 4]) >> 9) + 1) / 2.0**24
+        G.append(-np.log(-np.log(u)))
+    v = lw.astype(np.float64) + np.array(G)
+    e = np.exp((v - v.max()) / tau)
+    return int(np.argmax(v)) + 1, e / e.sum()
+
+
+def test_straight_through_dwell_gradient_of_an_initial_infection():
+    """One agent, initially infected, no contacts: its removal falls on day
+    b - 1 for the drawn I length b, and the straight-through gradient of the
+    loss with respect to the I log weight j is
+    (2/K) sum_t (D_t - y_t) m dc_{t+1}, with dc_k = c_k (delta_kj - c_j) / tau
+    the tangent of the relaxed one-hot c of the same Gumbel noise."""
+    K, m, tau = 10, float(np.float32(0.3)), 0.5  # parameters are float32 values
+    tgt = np.linspace(0.0, 0.2, K)
+    seed = next(s for s in range(100) if O.uniform(s, 0, 0xFFFFFFFF, 0) < 0.5)
+    dirs = O.dwell_directions(K, 1, 3, 5)
+    r = O.run(age=np.zeros(1, np.uint8), pop_offsets=[0, 1], src=[], dst=[], w=[], K=K, R=2.0, S=[1.0], m=m,
+              i0=0.5, Z=[1.0], mode=O.HARD_ST, tau_g=tau, seed=seed, target=tgt, directions=dirs, dwell=DWELL)
+    b, c = _relaxed_one_hot(DWELL[1], seed, 0, 0xFFFFFFFF, O.TAG_DWELL_I, tau)
+    assert r["drm"][b - 1] == 1.0 and r["drm"].sum() == 1.0
+    resid = r["deaths"] - tgt
+    for j in range(5):
+        dc = c * ((np.arange(5) == j) - c[j]) / tau
+        want = 2.0 / K * sum(resid[t] * m * dc[t] for t in range(min(K, 5)))
+        assert r["dL"][4 + 3 + j] == pytest.approx(want, rel=1e-12, abs=1e-15), j  # after R, S, m, i0, 3 E
+    assert np.all(r["dL"][4:7] == 0.0)  # no exposures: the E weights do not matter
