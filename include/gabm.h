@@ -305,6 +305,11 @@ typedef struct {
   double *dS;   /* device [n_sets*n_age] */
   double *dm;   /* device [n_sets] */
   double *di0;  /* device [n_sets] */
+  double *ddwell_E; /* device [tau_E] straight-through gradient with respect to the dwell log weights
+                       of the E lengths (Gumbel-softmax rule: the drawn one-hot forward, the tangent of
+                       softmax((lw + G) / tau_g) with the same noise G, Section 3.1), summed over every
+                       exposure; simulations created with dwell tables in HARD_ST mode; NULL: skip */
+  double *ddwell_I; /* device [tau_I] the same for the I lengths (exposures and initial infections) */
 } gabm_grads;
 
 /* Reverse pass of the last gabm_sim_forward (same p and rng): gradients of

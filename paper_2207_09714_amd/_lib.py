@@ -81,7 +81,8 @@ class FwdOut(C.Structure):
 
 
 class Grads(C.Structure):
-    _fields_ = [("dR", C.c_void_p), ("dS", C.c_void_p), ("dm", C.c_void_p), ("di0", C.c_void_p)]
+    _fields_ = [("dR", C.c_void_p), ("dS", C.c_void_p), ("dm", C.c_void_p), ("di0", C.c_void_p),
+                ("ddwell_E", C.c_void_p), ("ddwell_I", C.c_void_p)]
 
 
 _lib = None

@@ -48,6 +48,59 @@ __device__ __forceinline__ int dwell_I(const DParams& P, Rng rng, uint32_t loc, 
                                        uint32_t stream) {
   return P.dwell_I ? dwell_draw(P.dwell_I, P.tau_I, rng, loc, day, TAG_DWELL_I, p, stream) : P.tau_I;
 }
+// The relaxed one-hot ch = softmax((lw + G) / tau) of the same draw (the
+// straight-through Gumbel-softmax of Jang, Gu & Poole 2017); returns the
+// drawn length.
+__device__ __forceinline__ int dwell_relaxed(const float* lw, int n, Rng rng, uint32_t loc, uint32_t day, uint32_t tag0,
+                                             uint32_t p, uint32_t stream, double tau, double* ch) {
+  int best = 0;
+  double bv = -INFINITY, mx = -INFINITY;
+  uint4 x = make_uint4(0u, 0u, 0u, 0u);
+  for (int k = 0; k < n; ++k) {
+    if ((k & 3) == 0) x = rng_block(rng, loc, day, tag0 + (uint32_t)(k >> 2), p, stream);
+    const uint32_t w = (k & 3) == 0 ? x.x : ((k & 3) == 1 ? x.y : ((k & 3) == 2 ? x.z : x.w));
+    const double v = (double)lw[k] - log(-log(unit_u(w)));
+    if (v > bv) {
+      bv = v;
+      best = k;
+    }
+    ch[k] = v / tau;
+    mx = fmax(mx, ch[k]);
+  }
+  double sum = 0.0;
+  for (int k = 0; k < n; ++k) {
+    ch[k] = exp(ch[k] - mx);
+    sum += ch[k];
+  }
+  for (int k = 0; k < n; ++k) ch[k] /= sum;
+  return best + 1;
+}
+
+// Straight-through gradient of the log weights of one draw: with g_j the
+// loss's sensitivity to the one-hot's component j, adds
+// c_j (g_j - <c, g>) / tau to acc[j] (the relaxed one-hot's Jacobian).
+__device__ __forceinline__ void st_categorical(const double* c, const double* g, int n, double tau, double* acc) {
+  double m = 0.0;
+  for (int j = 0; j < n; ++j) m += c[j] * g[j];
+  for (int j = 0; j < n; ++j) {
+    const double v = c[j] * (g[j] - m) / tau;
+    if (v != 0.0) atomicAdd(&acc[j], v);
+  }
+}
+
+// Sensitivities of the loss to the E and I one-hots of an exposure on day d
+// with drawn lengths aS, bS: pre[k] = sum of the rate-adjoint ring over the
+// k days after d (k = 0..W), DR(x) = m Dbar of day d + x (0 past the run).
+// An E length a puts E on days 1..a, I on a+1..a+bS and the removal on a+bS;
+// an I length b puts I on aS+1..aS+b and the removal on aS+b.
+template <class DRF>
+__device__ __forceinline__ void dwell_sensitivities(const DParams& P, const double* pre, int aS, int bS, DRF DR,
+                                                    double* gE, double* gI) {
+  for (int a = 1; a <= P.tau_E; ++a)
+    gE[a - 1] = P.TE * pre[a] + P.TI * (pre[a + bS] - pre[a]) + DR(a + bS);
+  for (int b = 1; b <= P.tau_I; ++b) gI[b - 1] = P.TI * (pre[aS + b] - pre[aS]) + DR(aS + b);
+}
+
 // exposure day held in a packed record (-1: none, or an initial infection)
 __device__ __forceinline__ int rec_eday(uint32_t r) { return (int)(int16_t)(r >> 16); }
 

@@ -477,7 +477,8 @@ static gabm_status sim_params(gabm_sim s, const gabm_params* p, DParams* P) {
   if (rc != GABM_OK) return rc;
   const Sim& S = s->s;
   GABM_CHECK(p->n_sets == S.n_sets && p->K == S.K && p->tau_E == S.tau_E && p->tau_I == S.tau_I &&
-                 p->mode == S.mode && (p->per_pop_params ? 1 : 0) == S.per_pop && (p->iota != nullptr) == S.has_iota,
+                 p->mode == S.mode && (p->per_pop_params ? 1 : 0) == S.per_pop && (p->iota != nullptr) == S.has_iota &&
+                     (p->dwell_E != nullptr) == S.has_dwell,
              GABM_EINVAL, "params layout differs from the one the simulation was created with");
   return GABM_OK;
 }

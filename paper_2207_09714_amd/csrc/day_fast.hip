@@ -412,8 +412,10 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
 template <bool POPS, bool DWELL>
 __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga) {
   __shared__ double sg[2 + 16];
+  __shared__ double sdw[DWELL ? 16 : 1];  // dwell log-weight gradients (E 0-7, I 8-15)
   const int tid = threadIdx.x;
   if (tid < 18) sg[tid] = 0.0;
+  if (DWELL && tid < 16) sdw[tid] = 0.0;
   const DGraph& G = a.G;
   const DParams& P = a.P;
   const int t = a.t;
@@ -461,6 +463,19 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
       const double Aday = (double)a.A_st[i];
       const AdjOut ad = agent_adjoint<true>(P, a.rng, a.stream, d, set, p, loc, age, Aday, (double)(fl & 1u),
                                             (double)((fl >> 1) & 1u), false, sE, sI, Sbar1, drm_bar);
+      if (DWELL && a.gdw && (fl & 3u) == 3u) {  // an exposure on day d: its drawn lengths' gradient
+        double cE[8], cI[8], pre[17], gE[8], gI[8];
+        const int aS = dwell_relaxed(P.dwell_E, P.tau_E, a.rng, loc, (uint32_t)d, TAG_DWELL_E, (uint32_t)p, a.stream,
+                                     P.tau, cE);
+        const int bS = dwell_relaxed(P.dwell_I, P.tau_I, a.rng, loc, (uint32_t)d, TAG_DWELL_I, (uint32_t)p, a.stream,
+                                     P.tau, cI);
+        pre[0] = 0.0;
+        for (int k = 1; k <= W; ++k) pre[k] = pre[k - 1] + (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+        auto DR = [&](int x) { return d + x < P.K ? m * a.Dbar[(int64_t)o * P.K + d + x] : 0.0; };
+        dwell_sensitivities(P, pre, aS, bS, DR, gE, gI);
+        st_categorical(cE, gE, P.tau_E, P.tau, sdw);
+        st_categorical(cI, gI, P.tau_I, P.tau, sdw + 8);
+      }
       a.Sbar[i] = (float)ad.Sbar;
       a.g_prev[i] = (float)ad.g;
       g_new = (double)(float)ad.g;
@@ -488,6 +503,16 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
         if (s_blk >= 0) atomicAdd(&sg[1], v);
         else atomicAdd(&a.gi0[(int64_t)set * kSlots + slot], v);
       }
+      if (DWELL && a.gdw && u < (double)P.i0[set]) {  // a hard initial infection: its I length's gradient
+        double cI[8], gI[8];
+        dwell_relaxed(P.dwell_I, P.tau_I, a.rng, loc, kDayInit, TAG_DWELL_I, (uint32_t)p, a.stream, P.tau, cI);
+        double run = 0.0;
+        for (int b = 1; b <= P.tau_I; ++b) {
+          run += (double)a.ring[(int64_t)((b - 1) % W) * G.N + i];
+          gI[b - 1] = P.TI * run + (b - 1 < P.K ? m * a.Dbar[(int64_t)o * P.K + b - 1] : 0.0);
+        }
+        st_categorical(cI, gI, P.tau_I, P.tau, sdw + 8);
+      }
     }
   }
   const unsigned long long bz = __ballot(on && g_new != 0.0);
@@ -502,6 +527,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
       atomicAdd(&a.gi0[(int64_t)s_blk * kSlots + slot], sg[1]);
     }
   }
+  if (DWELL && a.gdw && tid < 16 && sdw[tid] != 0.0) atomicAdd(&a.gdw[tid * kSlots + slot], sdw[tid]);
 }
 
 template __global__ void k_agent_fwd<false, false>(FwdArgs<float>, SliceSums);

@@ -89,6 +89,7 @@ struct BwdArgs {
   double* gR;          // [n_sets][K][kSlots]
   double* gS;          // [n_sets][n_age][kSlots]
   double* gi0;         // [n_sets][kSlots]
+  double* gdw = nullptr;  // [16][kSlots] straight-through gradient of the dwell log weights (E 0-7, I 8-15), or null
 };
 
 // non-zero masks of the rate adjoint g for the persistent reverse kernel
@@ -113,6 +114,9 @@ struct FinBwdArgs {
   int K, n_age, n_out, n_sets;
   const double *gR, *gS, *gi0, *Dbar, *drm_int;
   double *dR, *dS, *dm, *di0;
+  const double* gdw = nullptr;  // dwell log-weight gradients: slots, then the outputs
+  double *ddw_E = nullptr, *ddw_I = nullptr;
+  int tau_E = 0, tau_I = 0;
 };
 
 __global__ void k_fill_u64(unsigned long long* p, int64_t n, unsigned long long v);
@@ -130,7 +134,7 @@ __global__ void k_er_vec(ErArgs a, const RT* v);
 __global__ void k_er_pairs_out(ErArgs a, int pop, int32_t* A, int32_t* B, int64_t cap);
 template <typename RT, bool SOFT>
 __global__ void k_day_fwd(FwdArgs<RT> a);
-template <typename RT, bool SOFT>
+template <typename RT, bool SOFT, bool DWELL>  // DWELL: stochastic dwell tables (hard modes)
 __global__ void k_day_bwd(BwdArgs<RT> a);
 // persistent neighbour sum over the fast tiles with an LDS-resident mask
 struct GatherArgs {

@@ -354,12 +354,14 @@ __global__ void __launch_bounds__(kBlock) k_day_fwd(FwdArgs<RT> a) {
 // neighbour sum is a gather over the same, symmetric CSR), then the agent
 // adjoint of day t-1 (straight-through or exact relaxed derivative), and on
 // t = 0 the adjoint of the initial infections.
-template <typename RT, bool SOFT>
+template <typename RT, bool SOFT, bool DWELL>
 __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
   __shared__ TileShared sh;
   __shared__ double sg[2 + 16];  // dR, di0, dS[n_age]
+  __shared__ double sdw[16];     // dwell log-weight gradients (E 0-7, I 8-15)
   const int tid = threadIdx.x;
   if (tid < 18) sg[tid] = 0.0;
+  if (tid < 16) sdw[tid] = 0.0;
   const DGraph& G = a.G;
   const DParams& P = a.P;
   const int t = a.t;
@@ -408,7 +410,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
         // inf_bar over the days after exposure on day d (E for dE days, then
         // I until day d + dL), weighted by the profile
         int dE = P.tau_E, dL = W;
-        if (P.dwell_E) {
+        if (DWELL && P.dwell_E) {
           dE = dwell_E(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
           dL = dE + dwell_I(P, a.rng, loc, (uint32_t)d, (uint32_t)p, a.stream);
         }
@@ -429,6 +431,19 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
         }
         const AdjOut ad = agent_adjoint<std::is_same<RT, float>::value>(P, a.rng, a.stream, d, set, p, loc, pre_age, A, Sv, h, SOFT, sE, sI, pre_Sbar,
                                         drm_bar);
+        if (DWELL && !SOFT && a.gdw && Sv != 0.0 && h != 0.0) {  // an exposure on day d: its drawn lengths' gradient
+          double cE[8], cI[8], pre[17], gE[8], gI[8];
+          const int aS = dwell_relaxed(P.dwell_E, P.tau_E, a.rng, loc, (uint32_t)d, TAG_DWELL_E, (uint32_t)p, a.stream,
+                                       P.tau, cE);
+          const int bS = dwell_relaxed(P.dwell_I, P.tau_I, a.rng, loc, (uint32_t)d, TAG_DWELL_I, (uint32_t)p, a.stream,
+                                       P.tau, cI);
+          pre[0] = 0.0;
+          for (int k = 1; k <= W; ++k) pre[k] = pre[k - 1] + (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+          auto DR = [&](int x) { return d + x < P.K ? m * a.Dbar[(int64_t)o * P.K + d + x] : 0.0; };
+          dwell_sensitivities(P, pre, aS, bS, DR, gE, gI);
+          st_categorical(cE, gE, P.tau_E, P.tau, sdw);
+          st_categorical(cI, gI, P.tau_I, P.tau, sdw + 8);
+        }
         a.Sbar[i] = (RT)ad.Sbar;
         const double lam_bar = ad.lam_bar;
         a.g_prev[i] = (RT)ad.g;
@@ -446,7 +461,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
       } else {
         // initial infections: x0_bar = T_I sum_{t<tau_I} inf_bar^t + m Dbar^{tau_I-1} - Sbar^0
         double sI = 0.0;  // day k is tau_E + 1 + k days after the initial infection's exposure
-        const int dI0 = dwell_I(P, a.rng, loc, kDayInit, (uint32_t)p, a.stream);
+        const int dI0 = DWELL ? dwell_I(P, a.rng, loc, kDayInit, (uint32_t)p, a.stream) : P.tau_I;
         for (int k = 0; k < dI0; ++k) sI += iota_at(P, P.tau_E + 1 + k) * (double)a.ring[(int64_t)(k % W) * G.N + i];
         const double x0_bar =
             P.TI * sI + ((dI0 - 1 < P.K) ? m * a.Dbar[(int64_t)o * P.K + dI0 - 1] : 0.0) - pre_Sbar;
@@ -457,6 +472,16 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
         if (v != 0.0) {
           if (o_tile >= 0) atomicAdd(&sg[1], v);
           else atomicAdd(&a.gi0[(int64_t)set * kSlots + slot], v);
+        }
+        if (DWELL && !SOFT && a.gdw && u < (double)P.i0[set]) {  // a hard initial infection: its I length's gradient
+          double cI[8], gI[8];
+          dwell_relaxed(P.dwell_I, P.tau_I, a.rng, loc, kDayInit, TAG_DWELL_I, (uint32_t)p, a.stream, P.tau, cI);
+          double run = 0.0;
+          for (int b = 1; b <= P.tau_I; ++b) {
+            run += (double)a.ring[(int64_t)((b - 1) % W) * G.N + i];
+            gI[b - 1] = P.TI * run + (b - 1 < P.K ? m * a.Dbar[(int64_t)o * P.K + b - 1] : 0.0);
+          }
+          st_categorical(cI, gI, P.tau_I, P.tau, sdw + 8);
         }
       }
     }
@@ -471,6 +496,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
         atomicAdd(&a.gi0[(int64_t)set * kSlots + slot], sg[1]);
       }
     }
+    if (DWELL && a.gdw && tid < 16 && sdw[tid] != 0.0) atomicAdd(&a.gdw[tid * kSlots + slot], sdw[tid]);
   };
   tile_pass(G, tb, sh, ev, epi);
 }
@@ -546,6 +572,13 @@ __global__ void k_fin_bwd(FinBwdArgs a) {
     a.di0[set] = s;
     a.dm[set] = dm;
   }
+  if (set == 0 && a.gdw && (int)threadIdx.x < 16) {
+    const int j = threadIdx.x;
+    double s = 0.0;
+    for (int k = 0; k < kSlots; ++k) s += a.gdw[j * kSlots + k];
+    if (j < 8 && j < a.tau_E && a.ddw_E) a.ddw_E[j] = s;
+    if (j >= 8 && j - 8 < a.tau_I && a.ddw_I) a.ddw_I[j - 8] = s;
+  }
 }
 
 // ----------------------------------------------------------------- explicit instantiations
@@ -557,10 +590,12 @@ template __global__ void k_day_fwd<float, false>(FwdArgs<float>);
 template __global__ void k_day_fwd<float, true>(FwdArgs<float>);
 template __global__ void k_day_fwd<double, false>(FwdArgs<double>);
 template __global__ void k_day_fwd<double, true>(FwdArgs<double>);
-template __global__ void k_day_bwd<float, false>(BwdArgs<float>);
-template __global__ void k_day_bwd<float, true>(BwdArgs<float>);
-template __global__ void k_day_bwd<double, false>(BwdArgs<double>);
-template __global__ void k_day_bwd<double, true>(BwdArgs<double>);
+template __global__ void k_day_bwd<float, false, false>(BwdArgs<float>);
+template __global__ void k_day_bwd<float, true, false>(BwdArgs<float>);
+template __global__ void k_day_bwd<double, false, false>(BwdArgs<double>);
+template __global__ void k_day_bwd<double, true, false>(BwdArgs<double>);
+template __global__ void k_day_bwd<float, false, true>(BwdArgs<float>);
+template __global__ void k_day_bwd<double, false, true>(BwdArgs<double>);
 template __global__ void k_er_vec<float>(ErArgs, const float*);
 template __global__ void k_er_vec<double>(ErArgs, const double*);
 

@@ -82,7 +82,7 @@ void Sim::release() {
   bwd_graphs.clear();
   void* ps[] = {rec[0], rec[1], maskI[0], maskI[1], maskI[2], maskE[0], maskE[1], maskE[2], A_er, Sv, x0, xi_ring,
                 inf[0], inf[1], A_st, fl_st, S_st, ck_rec, ck_soft, cnt, cnt0, drm, Dbar, Dbar_eff, ring, Sbar, g[0], g[1],
-                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece, anyI[0], anyI[1], anyI[2], wq, loc_P};
+                infbar_er, gR, gS, gi0, gz[0], gz[1], gz[2], Abuf, piece, anyI[0], anyI[1], anyI[2], wq, loc_P, gdw};
   for (void* p : ps) hipFree(p);
 }
 
@@ -136,6 +136,7 @@ static size_t extra_bytes(const Sim& s) {
   size_t b = 3 * s.gz_bytes;
   if (s.fast_fwd_ok || s.fast_bwd_ok) b += (size_t)G.n_slices * G.N * 8 + (size_t)G.slice_chunk.back() * 16;
   if (s.B > 1) b += 3 * (size_t)s.any_words * 8 + (size_t)(3 * s.K + 1) * 4;
+  if (s.has_dwell && s.mode == GABM_HARD_ST) b += (size_t)16 * kSlots * 8;
   return b;
 }
 
@@ -170,6 +171,7 @@ static void sim_shape(Sim& s, const Graph& G, const gabm_params* p, const gabm_r
     s.n_cu = ncu;
   }
   s.has_iota = p->iota != nullptr;
+  s.has_dwell = p->dwell_E != nullptr;
   const bool fast_shape = s.schedule == 0 && !s.has_iota && s.n_cu > 0 && s.B == 1 && G.n_slices > 0 &&
                           run->precision == GABM_F32 && s.mode != GABM_SOFT;
   s.fast_fwd_ok = fast_shape;
@@ -285,6 +287,7 @@ gabm_status sim_create(const Graph& G, const gabm_params* p, const gabm_run_desc
   AL(s.g[1], L.g);
   AL(s.infbar_er, L.ier);
   AL(s.loc_P, L.locp);
+  if (s.has_dwell && s.mode == GABM_HARD_ST) AL(s.gdw, (size_t)16 * kSlots * 8);
   AL(s.gR, L.gR);
   AL(s.gS, L.gS);
   AL(s.gi0, L.gi0);
@@ -564,6 +567,7 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.fl_st = (t >= 1 && !soft) ? s.fl_st + (int64_t)slot * s.NV : nullptr;
   a.S_st = (t >= 1 && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.Dbar = s.Dbar_eff; a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
+  a.gdw = s.gdw;
   if (std::is_same<RT, float>::value && s.fast_bwd_ok) {
     FastMasks fm;
     fm.cur = s.gz[t % 3];
@@ -587,8 +591,9 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     }
   } else {
     KTime kt(s, st, GABM_KT_DAY_BWD);
-    if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
-    else hipLaunchKernelGGL((k_day_bwd<RT, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+    if (soft) hipLaunchKernelGGL((k_day_bwd<RT, true, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+    else if (P.dwell_E) hipLaunchKernelGGL((k_day_bwd<RT, false, true>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
+    else hipLaunchKernelGGL((k_day_bwd<RT, false, false>), dim3(G.n_tiles), dim3(kBlock), 0, st, a);
   }
 }
 
@@ -597,6 +602,7 @@ static void fin_bwd(Sim& s, const gabm_grads* out, hipStream_t st) {
   f.K = s.K; f.n_age = s.n_age; f.n_out = sim_n_out(s); f.n_sets = s.n_sets;
   f.gR = s.gR; f.gS = s.gS; f.gi0 = s.gi0; f.Dbar = s.Dbar_eff; f.drm_int = s.drm;
   f.dR = out->dR; f.dS = out->dS; f.dm = out->dm; f.di0 = out->di0;
+  f.gdw = s.gdw; f.ddw_E = out->ddwell_E; f.ddw_I = out->ddwell_I; f.tau_E = s.tau_E; f.tau_I = s.tau_I;
   hipLaunchKernelGGL(k_fin_bwd, dim3(s.n_sets), dim3(kBlock), 0, st, f);
 }
 
@@ -736,6 +742,7 @@ static void bwd_reset(Sim& s, const double* lw, const double* db, hipStream_t st
   fill0(s.gR, (size_t)s.n_sets * s.K * kSlots * 8, st);
   fill0(s.gS, (size_t)s.n_sets * s.n_age * kSlots * 8, st);
   fill0(s.gi0, (size_t)s.n_sets * kSlots * 8, st);
+  fill0(s.gdw, s.gdw ? (size_t)16 * kSlots * 8 : 0, st);
 }
 
 // ---------------------------------------------------------------- day loops of a run

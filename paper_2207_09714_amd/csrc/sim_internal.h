@@ -58,6 +58,8 @@ struct Sim {
   double* gR = nullptr;   // [n_sets][K][kSlots]
   double* gS = nullptr;   // [n_sets][n_age][kSlots]
   double* gi0 = nullptr;  // [n_sets][kSlots]
+  double* gdw = nullptr;  // [16][kSlots] dwell log-weight gradients (runs created with dwell tables)
+  bool has_dwell = false;
 
   // kernel timing: event pairs around each fused day kernel
   int32_t time_kernels = 0;

@@ -276,6 +276,11 @@ class Simulator:
         self.dS = torch.zeros(self.n_sets, graph.n_age, dtype=torch.float64, device=dev)
         self.dm = torch.zeros(self.n_sets, dtype=torch.float64, device=dev)
         self.di0 = torch.zeros(self.n_sets, dtype=torch.float64, device=dev)
+        # straight-through gradients of the dwell log weights (HARD_ST runs with dwell tables)
+        self.ddwell = None
+        if dwell is not None and mode == HARD_ST:
+            self.ddwell = (torch.zeros(tau_E, dtype=torch.float64, device=dev),
+                           torch.zeros(tau_I, dtype=torch.float64, device=dev))
 
     def workspace_size(self) -> int:
         pb = self.params(torch.zeros(self.n_sets, self.K), torch.zeros(self.n_sets, self.graph.n_age),
@@ -296,6 +301,8 @@ class Simulator:
     def _grads(self):
         g = L.Grads()
         g.dR, g.dS, g.dm, g.di0 = self.dR.data_ptr(), self.dS.data_ptr(), self.dm.data_ptr(), self.di0.data_ptr()
+        if self.ddwell is not None:
+            g.ddwell_E, g.ddwell_I = self.ddwell[0].data_ptr(), self.ddwell[1].data_ptr()
         return g
 
     @staticmethod
@@ -325,7 +332,10 @@ class Simulator:
         g = self._grads()
         check(lib().gabm_sim_backward(self.handle, C.byref(params.c), C.byref(rng), _ptr(lw), _ptr(db),
                                       C.byref(g), C.c_void_p(_stream(stream))))
-        return dict(dR=self.dR, dS=self.dS, dm=self.dm, di0=self.di0)
+        out = dict(dR=self.dR, dS=self.dS, dm=self.dm, di0=self.di0)
+        if self.ddwell is not None:
+            out["ddwell_E"], out["ddwell_I"] = self.ddwell
+        return out
 
     def day_fwd(self, params: ParamBlock, day, seed=0, replicate=0, target=None, stream=None, independent_sets=False):
         rng = make_rng(seed, replicate, independent_sets)

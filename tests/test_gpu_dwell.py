@@ -193,3 +193,46 @@ def test_full_size_c3_with_dwell(G, O):
     assert np.array_equal(counts, ref["counts"])
     assert np.array_equal(drm, ref["drm"])
     assert np.array_equal(last, ref["stage"][-1])
+
+
+@pytest.mark.parametrize("precision,schedule", [(0, 0), (0, 1), (1, 0)], ids=["f32-split", "f32-tiles", "f64"])
+def test_dwell_weight_gradients_match_oracle(G, O, precision, schedule):
+    """Straight-through Gumbel-softmax gradients with respect to the dwell log
+    weights (every exposure's E and I one-hots and every initial infection's I
+    one-hot, through the relaxed one-hot of the same noise) against the
+    oracle's forward-mode tangents along each log weight."""
+    wl = make_workload("c2", n_agents=6000, K=30)
+    tgt = np.linspace(0.0, 0.6, wl.K)
+    _say(f"dwell weight gradients N={wl.n_agents} K={wl.K} precision={precision} schedule={schedule}")
+    g = graph_of(G, wl)
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.HARD_ST, precision=precision, ckpt_every=7, tau_g=wl.tau_g,
+                      schedule=schedule, dwell=DWELL)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    sim.forward(pb, seed=wl.seed, target=torch.tensor(tgt, device="cuda"))
+    gr = sim.backward(pb, seed=wl.seed)
+    dirs = O.dwell_directions(wl.K, 8, 3, 5)
+    ref = O.run_workload(wl, mode=O.HARD_ST, target=tgt, directions=dirs, dwell=DWELL)
+    want = ref["dL"][11:]
+    got = np.concatenate([gr["ddwell_E"].cpu().numpy(), gr["ddwell_I"].cpu().numpy()])
+    assert np.max(np.abs(want)) > 0
+    assert_grads(got, want)
+    assert_grads(grads_vec(gr), ref["dL"][:11])  # the other gradients are unchanged by the extra outputs
+
+
+def test_dwell_weight_gradients_on_packed_populations(G, O):
+    """One table for all populations: its gradient is the sum of each
+    population's oracle tangents."""
+    wl = make_workload("c4b", n_agents=5000, K=20, n_pops=3)
+    P = wl.pop.n_pops
+    tgt = np.linspace(0.0, 0.5, wl.K)
+    g = graph_of(G, wl)
+    sim = G.Simulator(g, n_sets=P, K=wl.K, Z=wl.Z, mode=G.HARD_ST, per_pop_params=True, ckpt_every=5,
+                      tau_g=wl.tau_g, dwell=DWELL)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    sim.forward(pb, seed=wl.seed, target=torch.tensor(tgt, device="cuda"))
+    gr = sim.backward(pb, seed=wl.seed)
+    dirs = O.dwell_directions(wl.K, 8, 3, 5)
+    want = sum(O.run_workload(wl, pop_index=p, mode=O.HARD_ST, target=tgt, directions=dirs, dwell=DWELL)["dL"][11:]
+               for p in range(P))
+    got = np.concatenate([gr["ddwell_E"].cpu().numpy(), gr["ddwell_I"].cpu().numpy()])
+    assert_grads(got, want)
