@@ -19,7 +19,11 @@
  * Parity pins: see the test-suite.  Every function here is pinned except the
  * exact form of the per-contact rate, which the paper defers to an external
  * reference (Section 3.1, after Eq. 3): "parity unpinned" against the paper
- * for the constant Z; pinned internally by closed forms.
+ * for the constant Z; pinned internally by closed forms.  Partly unpinned:
+ * the straight-through tangent along the dwell log weights of an exposure's
+ * drawn lengths ("parity unpinned" on its own) shares its bilinear
+ * window-tangent code with the relaxed mode, which finite differences pin;
+ * the initial infections' part has a closed-form pin.
  */
 #ifndef GABM_ORACLE_H
 #define GABM_ORACLE_H
