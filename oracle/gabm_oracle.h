@@ -20,10 +20,11 @@
  * exact form of the per-contact rate, which the paper defers to an external
  * reference (Section 3.1, after Eq. 3): "parity unpinned" against the paper
  * for the constant Z; pinned internally by closed forms.  Partly unpinned:
- * the straight-through tangent along the dwell log weights of an exposure's
+ * the straight-through tangent along the I log weights of an exposure's
  * drawn lengths ("parity unpinned" on its own) shares its bilinear
  * window-tangent code with the relaxed mode, which finite differences pin;
- * the initial infections' part has a closed-form pin.
+ * the E weights of an exposure and the initial infections' I weights have
+ * closed-form pins.
  */
 #ifndef GABM_ORACLE_H
 #define GABM_ORACLE_H

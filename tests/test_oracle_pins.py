@@ -692,3 +692,40 @@ def test_straight_through_dwell_gradient_of_an_initial_infection():
         want = 2.0 / K * sum(resid[t] * m * dc[t] for t in range(min(K, 5)))
         assert r["dL"][4 + 3 + j] == pytest.approx(want, rel=1e-12, abs=1e-15), j  # after R, S, m, i0, 3 E
     assert np.all(r["dL"][4:7] == 0.0)  # no exposures: the E weights do not matter
+
+
+def test_straight_through_dwell_gradient_of_an_exposure():
+    """Two agents in contact: agent 0 initially infected, agent 1 exposed on
+    day u.  Along the E log weights nothing but agent 1's removal moves
+    (agent 0 has no E length and is no longer susceptible), and agent 1's
+    removal falls on day u + a + b for its drawn lengths, so the gradient with
+    respect to E log weight j is (2/K) sum_k (D_{u+k} - y_{u+k}) m dc_{k-b},
+    dc the relaxed one-hot's tangent of agent 1's E draw."""
+    K, m, tau = 20, float(np.float32(0.3)), 0.5
+    tgt = np.linspace(0.0, 0.2, K)
+    kw = dict(age=np.zeros(2, np.uint8), pop_offsets=[0, 2], src=[0, 1], dst=[1, 0], w=[1.0, 1.0], K=K, R=3.0,
+              S=[1.0], m=m, i0=0.5, Z=[1.0], mode=O.HARD_ST, tau_g=tau, target=tgt, dwell=DWELL)
+    for seed in range(400):
+        if not (O.uniform(seed, 0, 0xFFFFFFFF, 0) < 0.5 <= O.uniform(seed, 1, 0xFFFFFFFF, 0)):
+            continue
+        r = O.run(seed=seed, want_agents=True, want_stage=True, **kw)
+        exposed = [t for t in range(K) if r["h"][t, 1] and r["stage"][t, 1] == 0]
+        if exposed and exposed[0] + 3 + 5 < K:
+            break
+    else:
+        pytest.skip("no seed with an early exposure")
+    u = exposed[0]
+    a, cE = _relaxed_one_hot(DWELL[0], seed, 1, u, O.TAG_DWELL_E, tau)
+    b, _ = _relaxed_one_hot(DWELL[1], seed, 1, u, O.TAG_DWELL_I, tau)
+    # E from snapshot u + 1, removed during day u + a + b
+    assert r["stage"][u + a + b + 1, 1] in (3, 4) and r["stage"][u + a + b, 1] == ST_I
+    dirs = O.dwell_directions(K, 1, 3, 5)
+    rd = O.run(seed=seed, directions=dirs, **kw)
+    resid = rd["deaths"] - tgt
+    wants = []
+    for j in range(3):
+        dc = cE * ((np.arange(3) == j) - cE[j]) / tau
+        want = sum(2.0 / K * resid[u + k] * m * dc[k - b - 1] for k in range(b + 1, b + 4) if u + k < K)
+        assert rd["dL"][4 + j] == pytest.approx(want, rel=1e-12, abs=1e-15), (j, rd["dL"][4 + j], want)
+        wants.append(want)
+    assert max(abs(w) for w in wants) > 1e-6
