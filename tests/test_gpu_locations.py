@@ -343,3 +343,34 @@ def test_full_size_c3_with_venues(G, O):
                 S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=Z, T=wl.T, mode=O.PLAIN, seed=wl.seed, visits=(va, vl, vw))
     assert np.array_equal(counts, ref["counts"])
     assert np.array_equal(drm, ref["drm"])
+
+
+def test_location_layer_edge_cases(G, O):
+    """Venues with a single visitor (they add nothing), zero-weight visits,
+    agents without visits, unused location ids above the largest one visited,
+    and visits listed in random order: trajectories equal the oracle's, and
+    the per-agent accumulators start clean on a second run."""
+    wl = make_workload("c1", n_agents=3000, K=16)
+    rng = np.random.default_rng(5)
+    n = wl.n_agents
+    members = rng.permutation(n)[: n // 2]  # half the agents visit nothing
+    va = np.concatenate([members, members[:200]]).astype(np.int32)
+    vl = np.concatenate([rng.integers(0, 60, len(members)), 60 + np.arange(200)]).astype(np.int32)  # 200 singletons
+    vw = (rng.integers(0, 33, len(va)) / 64.0).astype(np.float32)  # some weights 0
+    order = rng.permutation(len(va))
+    visits = (va[order], vl[order], vw[order])
+    deg = location_degree(n, visits)
+    Z = (wl.Z + np.float32(wl.tau_I * deg.mean())).astype(np.float32)
+    _say(f"location edge cases N={n} V={len(va)}")
+    g = G.Graph(n_agents=n, src=wl.src, dst=wl.dst, w=wl.w, age=wl.pop.age, er_mean_deg=wl.er_mean_deg,
+                er_weight=wl.er_weight, visits=visits, n_locations=400)
+    assert g.info()["n_locations"] == 400
+    sim = G.Simulator(g, K=wl.K, Z=Z, mode=G.HARD_ST, ckpt_every=4, tau_g=wl.tau_g)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    ref = O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=wl.R[0],
+                S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=Z, T=wl.T, mode=O.HARD_ST, tau_g=wl.tau_g, seed=wl.seed,
+                er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, visits=visits)
+    for rep in range(2):
+        out = sim.forward(pb, seed=wl.seed)
+        assert np.array_equal(out["counts"][0].cpu().numpy(), ref["counts"]), rep
+        sim.backward(pb, seed=wl.seed)
