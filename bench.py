@@ -472,17 +472,18 @@ def locations_leg(gabm, torch, wl, g0_ms, steps: int = 2, warmup: int = 1):
     ck = wl.ckpt_every
     n_seg = (wl.K + ck - 1) // ck if ck else 1
     per_step = 2 * wl.K + (n_seg - 1) * ck
-    # one pass: visits read twice (location order: location, agent, weight;
-    # agent order: location, weight) with a 4-byte value and an 8-byte
-    # pressure read per visit; per agent its visit offset, its value and a
-    # read-modify-write of its sum; per location the clearing and one atomic
-    ab = 28.0 * V + 28.0 * wl.n_agents + 24.0 * nl
+    # one timed pass on the split kernels is the pressure kernel (the per-agent
+    # sums are folded into the agent kernels): per visit its location, agent
+    # and weight and the visitor's 4-byte value; per location one atomic
+    # (read and write)
+    ab = 16.0 * V + 16.0 * nl
     return {"workload": f"{wl.name} + agent-location layer: {V} visits to {nl} venues (schools, workplaces, "
                         f"leisure), standing for {expanded} directed contacts",
             "visits": V, "locations": nl, "expanded_contacts": expanded, "ms_per_step": dt * 1e3,
             "ms_per_step_without_layer": g0_ms,
             "loc_pass": {"launches_per_step": per_step, "avg_ms": avg * 1e3, "ms_per_step": avg * 1e3 * per_step,
-                         "alg_bytes_per_launch": ab, "alg_GBps": ab / avg / 1e9},
+                         "alg_bytes_per_launch": ab, "alg_GBps": ab / avg / 1e9,
+                         "note": "k_loc_pressure; the per-agent sums run inside the split agent kernels"},
             "timing": f"eager launches; HIP events around every {TIME_EVERY}th launch of each kernel class"}
 
 

@@ -23,6 +23,7 @@
 // occupancy instead of inside the streaming loop.
 #include "agent.h"
 #include "day_kernels.h"
+#include "loc.h"
 
 namespace gabm {
 
@@ -343,7 +344,7 @@ __device__ __forceinline__ double gathered(const SliceSums& ga, int i) {
 // day t+1, counts.  Packed populations: each agent uses its population's
 // normaliser and parameter set and counts into its output; a block whose
 // agents share one output reduces its counts first.
-template <bool POPS, bool DWELL>
+template <bool POPS, bool DWELL, bool LOC>
 __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSums ga) {
   __shared__ unsigned scnt[kCnt];
   const int tid = threadIdx.x;
@@ -354,6 +355,9 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
   // clear the masks of day t+2 (read last on day t-1, written next on day t+1)
   for (int64_t x = blockIdx.x * (int64_t)kBlock + tid; x < a.mask_words; x += (int64_t)gridDim.x * kBlock)
     a.mI_clr[x] = 0ull;
+  if (LOC)  // the location pressures of the next pass start at zero
+    for (int64_t l = blockIdx.x * (int64_t)kBlock + tid; l < a.lf.n_loc; l += (int64_t)gridDim.x * kBlock)
+      a.lf.P_next[l] = 0.0;
   __syncthreads();
   const int i = blockIdx.x * kBlock + tid;
   const bool on = i < G.N;
@@ -372,6 +376,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
       A += a.A_er[i];
       a.A_er[i] = 0.0;
     }
+    if (LOC) A += loc_agent_sum(a.lf, i, P.TI * (double)mask_bit(a.mI_cur, i));
     if (a.A_st) a.A_st[i] = (float)A;
     const HardDay hd = hard_agent_day<DWELL>(P, a.rng, a.stream, t, set, p, loc, G.age[i], A, a.rec_in[i], nullptr);
     if (a.fl_st) a.fl_st[i] = (uint8_t)((hd.was_s ? 1u : 0u) | (hd.h ? 2u : 0u));
@@ -409,7 +414,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_fwd(FwdArgs<float> a, SliceSum
 // then the adjoint of day t-1 (t >= 1) or of the initial infections (t = 0);
 // g^{t-1} and its non-zero mask for the next step's gather.  Parameter-gradient
 // partials are reduced per block when its agents share one parameter set.
-template <bool POPS, bool DWELL>
+template <bool POPS, bool DWELL, bool LOC>
 __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga) {
   __shared__ double sg[2 + 16];
   __shared__ double sdw[DWELL ? 16 : 1];  // dwell log-weight gradients (E 0-7, I 8-15)
@@ -422,6 +427,9 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
   const int W = P.tau_E + P.tau_I;
   for (int64_t x = blockIdx.x * (int64_t)kBlock + tid; x < fm.words; x += (int64_t)gridDim.x * kBlock)
     fm.clr[x] = 0ull;
+  if (LOC)  // the location pressures of the next pass start at zero
+    for (int64_t l = blockIdx.x * (int64_t)kBlock + tid; l < a.lf.n_loc; l += (int64_t)gridDim.x * kBlock)
+      a.lf.P_next[l] = 0.0;
   __syncthreads();
   const int i = blockIdx.x * kBlock + tid;
   const bool on = i < G.N;
@@ -441,6 +449,7 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
         infbar += a.infbar_er[i];
         a.infbar_er[i] = 0.0;
       }
+      if (LOC) infbar += loc_agent_sum(a.lf, i, (double)a.g_cur[i]);
       a.ring[(int64_t)(t % W) * G.N + i] = (float)infbar;
     }
     const int age = G.age[i];
@@ -530,14 +539,22 @@ __global__ void __launch_bounds__(kBlock) k_agent_bwd(BwdArgs<float> a, FastMask
   if (DWELL && a.gdw && tid < 16 && sdw[tid] != 0.0) atomicAdd(&a.gdw[tid * kSlots + slot], sdw[tid]);
 }
 
-template __global__ void k_agent_fwd<false, false>(FwdArgs<float>, SliceSums);
-template __global__ void k_agent_fwd<true, false>(FwdArgs<float>, SliceSums);
-template __global__ void k_agent_fwd<false, true>(FwdArgs<float>, SliceSums);
-template __global__ void k_agent_fwd<true, true>(FwdArgs<float>, SliceSums);
-template __global__ void k_agent_bwd<false, false>(BwdArgs<float>, FastMasks, SliceSums);
-template __global__ void k_agent_bwd<true, false>(BwdArgs<float>, FastMasks, SliceSums);
-template __global__ void k_agent_bwd<false, true>(BwdArgs<float>, FastMasks, SliceSums);
-template __global__ void k_agent_bwd<true, true>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_fwd<false, false, false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<false, false, true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<false, true, false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<false, true, true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true, false, false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true, false, true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true, true, false>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_fwd<true, true, true>(FwdArgs<float>, SliceSums);
+template __global__ void k_agent_bwd<false, false, false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<false, false, true>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<false, true, false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<false, true, true>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true, false, false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true, false, true>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true, true, false>(BwdArgs<float>, FastMasks, SliceSums);
+template __global__ void k_agent_bwd<true, true, true>(BwdArgs<float>, FastMasks, SliceSums);
 template __global__ void k_gather_fast<false>(GatherArgs);
 template __global__ void k_gather_fast<true>(GatherArgs);
 

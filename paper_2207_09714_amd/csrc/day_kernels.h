@@ -38,6 +38,18 @@ struct ErArgs {
   int tau_E = 0, W = 0;
 };
 
+// The agent-location layer's per-agent sum folded into the split agent
+// kernels: the day's pressures, the buffer to clear for the next pass, and the
+// agent-sorted visits (P null: not folded).
+struct LocFuse {
+  const double* P = nullptr;
+  double* P_next = nullptr;
+  const int64_t* av_ptr = nullptr;
+  const int32_t* av_loc = nullptr;
+  const float* av_w = nullptr;
+  int32_t n_loc = 0;
+};
+
 template <typename RT>
 struct FwdArgs {
   DGraph G;
@@ -67,6 +79,7 @@ struct FwdArgs {
   RT* S_st;
   double* cnt;  // [n_out][K][kSlots][kCnt] or NULL (no counting)
   double* lam_out;
+  LocFuse lf;  // split agent kernel only
 };
 
 template <typename RT>
@@ -90,6 +103,7 @@ struct BwdArgs {
   double* gS;          // [n_sets][n_age][kSlots]
   double* gi0;         // [n_sets][kSlots]
   double* gdw = nullptr;  // [16][kSlots] straight-through gradient of the dwell log weights (E 0-7, I 8-15), or null
+  LocFuse lf;             // split agent kernel only
 };
 
 // non-zero masks of the rate adjoint g for the persistent reverse kernel
@@ -172,10 +186,11 @@ inline SliceSums slice_sums(const GatherArgs& a) {
 template <bool BWD>
 __global__ void k_gather_fast(GatherArgs a);
 // POPS: several populations (per-agent population, parameter set and output)
-// DWELL: the parameters may carry stochastic dwell tables
-template <bool POPS, bool DWELL>
+// DWELL: the parameters may carry stochastic dwell tables; LOC: the
+// agent-location layer's per-agent sum is folded in (a.lf)
+template <bool POPS, bool DWELL, bool LOC>
 __global__ void k_agent_fwd(FwdArgs<float> a, SliceSums ga);
-template <bool POPS, bool DWELL>
+template <bool POPS, bool DWELL, bool LOC>
 __global__ void k_agent_bwd(BwdArgs<float> a, FastMasks fm, SliceSums ga);
 __global__ void k_fin_fwd(FinArgs a);
 __global__ void k_dbar_eff(int n_out, int K, const double* Dbar, const double* w, const double* db, double* out);

@@ -10,6 +10,7 @@
 // expanded graph needs the sum of squared location sizes.
 #pragma once
 
+#include "day_kernels.h"
 #include "gabm_device.h"
 
 namespace gabm {
@@ -106,6 +107,20 @@ __global__ void __launch_bounds__(kBlock) k_loc_gather(LocView L, V val, const d
     }
     if (s != 0.0) acc[i] += s;
   }
+}
+
+// The per-agent sum of k_loc_gather for one agent, inside another kernel
+// (same arithmetic, no contraction).
+__device__ __forceinline__ double loc_agent_sum(const LocFuse& L, int64_t i, double xi) {
+#pragma clang fp contract(off)
+  const int64_t b = L.av_ptr[i], e = L.av_ptr[i + 1];
+  double s = 0.0;
+  for (int64_t k = b; k < e; ++k) {
+    const double w = (double)L.av_w[k];
+    const double own = xi != 0.0 ? w * xi : 0.0;
+    s += w * (L.P[L.av_loc[k]] - own);
+  }
+  return s;
 }
 
 }  // namespace gabm

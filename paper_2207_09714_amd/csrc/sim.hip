@@ -356,9 +356,11 @@ static GatherArgs gather_args(const Sim& s, const DGraph& dg, const unsigned lon
   return ga;
 }
 
-// the agent-location layer's two passes for one day, adding into `acc`
+// the agent-location layer's two passes for one day, adding into `acc`; with
+// `fold` set only the pressures are formed here and `fold` receives what the
+// split agent kernel needs to add the per-agent sums itself
 template <class V>
-static void loc_pass(Sim& s, const V& val, double* acc, hipStream_t st) {
+static void loc_pass(Sim& s, const V& val, double* acc, hipStream_t st, LocFuse* fold = nullptr) {
   const Graph& G = *s.G;
   LocView L;
   L.N = G.N; L.n_loc = G.n_loc; L.V = G.n_visits;
@@ -371,8 +373,17 @@ static void loc_pass(Sim& s, const V& val, double* acc, hipStream_t st) {
   double* P = s.loc_P + (size_t)s.loc_par * G.n_loc;
   double* Pn = s.loc_P + (size_t)(1 - s.loc_par) * G.n_loc;
   hipLaunchKernelGGL(k_loc_pressure<V>, dim3(blocks_capped(G.n_visits)), dim3(kBlock), 0, st, L, val, P);
-  hipLaunchKernelGGL(k_loc_gather<V>, dim3(blocks_capped(std::max<int64_t>(G.N, G.n_loc))), dim3(kBlock), 0, st, L,
-                     val, (const double*)P, acc, Pn);
+  if (fold) {
+    fold->P = P;
+    fold->P_next = Pn;
+    fold->av_ptr = G.av_ptr;
+    fold->av_loc = G.av_loc;
+    fold->av_w = G.av_w;
+    fold->n_loc = G.n_loc;
+  } else {
+    hipLaunchKernelGGL(k_loc_gather<V>, dim3(blocks_capped(std::max<int64_t>(G.N, G.n_loc))), dim3(kBlock), 0, st, L,
+                       val, (const double*)P, acc, Pn);
+  }
   s.loc_par = 1 - s.loc_par;
 }
 
@@ -426,6 +437,8 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     else hipLaunchKernelGGL(k_er_fwd_hard, dim3(nb), dim3(kBlock), 0, st, e, (const uint32_t*)s.maskI[t % 3],
                             withE ? (const uint32_t*)s.maskE[t % 3] : nullptr);
   }
+  const bool fast = std::is_same<RT, float>::value && s.fast_fwd_ok && !withE;
+  LocFuse lf;
   if (G.n_visits > 0) {
     if (soft) {
       LocVecVal<RT> v;
@@ -444,7 +457,7 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
         v.tau_E = P.tau_E;
         v.W = P.tau_E + P.tau_I;
       }
-      loc_pass(s, v, s.A_er, st);
+      loc_pass(s, v, s.A_er, st, fast ? &lf : nullptr);  // the split agent kernel adds the sums
     }
   }
   FwdArgs<RT> a;
@@ -467,7 +480,8 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.S_st = (store && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.cnt = count ? s.cnt : nullptr;
   a.lam_out = nullptr;
-  if (std::is_same<RT, float>::value && s.fast_fwd_ok && !withE) {
+  a.lf = lf;
+  if (fast) {
     const GatherArgs ga = gather_args(s, dg, s.maskI[t % 3], nullptr, P.TI);
     {
       KTime kt(s, st, GABM_KT_GATHER_FWD);
@@ -476,12 +490,17 @@ static void b1_day_fwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     KTime kt(s, st, GABM_KT_AGENT_FWD);
     const FwdArgs<float>& af = *(FwdArgs<float>*)&a;
     const dim3 grid(blocks_for(G.N)), blk(kBlock);
-    if (P.dwell_E) {
-      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_fwd<true, true>), grid, blk, 0, st, af, slice_sums(ga));
-      else hipLaunchKernelGGL((k_agent_fwd<false, true>), grid, blk, 0, st, af, slice_sums(ga));
-    } else {
-      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_fwd<true, false>), grid, blk, 0, st, af, slice_sums(ga));
-      else hipLaunchKernelGGL((k_agent_fwd<false, false>), grid, blk, 0, st, af, slice_sums(ga));
+    const SliceSums ss = slice_sums(ga);
+    const int variant = (G.n_pops > 1 ? 4 : 0) | (P.dwell_E ? 2 : 0) | (lf.P ? 1 : 0);
+    switch (variant) {
+      case 0: hipLaunchKernelGGL((k_agent_fwd<false, false, false>), grid, blk, 0, st, af, ss); break;
+      case 1: hipLaunchKernelGGL((k_agent_fwd<false, false, true>), grid, blk, 0, st, af, ss); break;
+      case 2: hipLaunchKernelGGL((k_agent_fwd<false, true, false>), grid, blk, 0, st, af, ss); break;
+      case 3: hipLaunchKernelGGL((k_agent_fwd<false, true, true>), grid, blk, 0, st, af, ss); break;
+      case 4: hipLaunchKernelGGL((k_agent_fwd<true, false, false>), grid, blk, 0, st, af, ss); break;
+      case 5: hipLaunchKernelGGL((k_agent_fwd<true, false, true>), grid, blk, 0, st, af, ss); break;
+      case 6: hipLaunchKernelGGL((k_agent_fwd<true, true, false>), grid, blk, 0, st, af, ss); break;
+      default: hipLaunchKernelGGL((k_agent_fwd<true, true, true>), grid, blk, 0, st, af, ss); break;
     }
   } else {
     KTime kt(s, st, GABM_KT_DAY_FWD);
@@ -552,10 +571,12 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     KTime ke(s, st, GABM_KT_ER);
     hipLaunchKernelGGL(k_er_vec<RT>, dim3(blocks_capped(dg.er_total)), dim3(kBlock), 0, st, e, (const RT*)s.g[t & 1]);
   }
+  const bool fastb = std::is_same<RT, float>::value && s.fast_bwd_ok;
+  LocFuse lf;
   if (gather && G.n_visits > 0) {
     LocVecVal<RT> v;
     v.v = (const RT*)s.g[t & 1];
-    loc_pass(s, v, s.infbar_er, st);
+    loc_pass(s, v, s.infbar_er, st, fastb ? &lf : nullptr);  // the split agent kernel adds the sums
   }
   BwdArgs<RT> a;
   a.G = dg; a.P = P; a.rng = rng; a.stream = stream; a.t = t; a.do_gather = gather ? 1 : 0;
@@ -568,7 +589,8 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
   a.S_st = (t >= 1 && soft) ? store_ptr<RT>(s.S_st, s, slot) : nullptr;
   a.Dbar = s.Dbar_eff; a.gR = s.gR; a.gS = s.gS; a.gi0 = s.gi0;
   a.gdw = s.gdw;
-  if (std::is_same<RT, float>::value && s.fast_bwd_ok) {
+  a.lf = lf;
+  if (fastb) {
     FastMasks fm;
     fm.cur = s.gz[t % 3];
     fm.next = s.gz[(t + 2) % 3];
@@ -582,12 +604,17 @@ static void b1_day_bwd(Sim& s, const DParams& P, Rng rng, uint32_t stream, int t
     KTime kt(s, st, GABM_KT_AGENT_BWD);
     const BwdArgs<float>& ab = *(BwdArgs<float>*)&a;
     const dim3 grid(blocks_for(G.N)), blk(kBlock);
-    if (P.dwell_E) {
-      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_bwd<true, true>), grid, blk, 0, st, ab, fm, slice_sums(ga));
-      else hipLaunchKernelGGL((k_agent_bwd<false, true>), grid, blk, 0, st, ab, fm, slice_sums(ga));
-    } else {
-      if (G.n_pops > 1) hipLaunchKernelGGL((k_agent_bwd<true, false>), grid, blk, 0, st, ab, fm, slice_sums(ga));
-      else hipLaunchKernelGGL((k_agent_bwd<false, false>), grid, blk, 0, st, ab, fm, slice_sums(ga));
+    const SliceSums ss = slice_sums(ga);
+    const int variant = (G.n_pops > 1 ? 4 : 0) | (P.dwell_E ? 2 : 0) | (lf.P ? 1 : 0);
+    switch (variant) {
+      case 0: hipLaunchKernelGGL((k_agent_bwd<false, false, false>), grid, blk, 0, st, ab, fm, ss); break;
+      case 1: hipLaunchKernelGGL((k_agent_bwd<false, false, true>), grid, blk, 0, st, ab, fm, ss); break;
+      case 2: hipLaunchKernelGGL((k_agent_bwd<false, true, false>), grid, blk, 0, st, ab, fm, ss); break;
+      case 3: hipLaunchKernelGGL((k_agent_bwd<false, true, true>), grid, blk, 0, st, ab, fm, ss); break;
+      case 4: hipLaunchKernelGGL((k_agent_bwd<true, false, false>), grid, blk, 0, st, ab, fm, ss); break;
+      case 5: hipLaunchKernelGGL((k_agent_bwd<true, false, true>), grid, blk, 0, st, ab, fm, ss); break;
+      case 6: hipLaunchKernelGGL((k_agent_bwd<true, true, false>), grid, blk, 0, st, ab, fm, ss); break;
+      default: hipLaunchKernelGGL((k_agent_bwd<true, true, true>), grid, blk, 0, st, ab, fm, ss); break;
     }
   } else {
     KTime kt(s, st, GABM_KT_DAY_BWD);
