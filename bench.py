@@ -41,8 +41,8 @@ KERNEL_SOURCES = ("day_kernels.hip", "day_fast.hip", "agent.h", "tile.h", "gabm_
 
 # kernel class -> device function name as rocprofv3 reports it
 KERNEL_NAMES = {
-    "gather_fwd": "k_gather_fast<false>", "agent_fwd": "k_agent_fwd<false, false>", "day_fwd": "k_day_fwd",
-    "gather_bwd": "k_gather_fast<true>", "agent_bwd": "k_agent_bwd<false, false>", "day_bwd": "k_day_bwd", "er": "k_er",
+    "gather_fwd": "k_gather_fast<false>", "agent_fwd": "k_agent_fwd<false, false, false>", "day_fwd": "k_day_fwd",
+    "gather_bwd": "k_gather_fast<true>", "agent_bwd": "k_agent_bwd<false, false, false>", "day_bwd": "k_day_bwd", "er": "k_er",
 }
 
 
