@@ -213,8 +213,9 @@ enum { GABM_INF_REC = 0,   /* gabm_rec[N]: T[stage] */
  * w * inf_j, plus the day's random layer (when the graph has one), and
  * lambda_i = R^day * S[a_i] * A_i / Z_p for parameter set `set`.  Sums are
  * formed in double precision.  A, lambda: device double[N] (lambda may be
- * NULL).  A graph with an agent-location layer: GABM_EUNSUPPORTED (that
- * layer runs in whole runs, gabm_sim_*, only). */
+ * NULL).  With an agent-location layer its two-hop sums are added too; their
+ * pressures use scratch memory owned by the graph, so such calls on one graph
+ * must not overlap (nor overlap gabm_transmit_bwd on it). */
 gabm_status gabm_transmit_fwd(gabm_graph g, const void *inf, int32_t inf_fmt, const gabm_params *p, int32_t set,
                               const gabm_rng *rng, int32_t day, double *A, double *lambda, void *stream);
 
@@ -237,8 +238,8 @@ gabm_status gabm_progress_stages(gabm_graph g, const gabm_rec *rec_in, const uin
 /* Backward of the neighbour sum (adjoint of gabm_transmit_fwd with respect
  * to inf): infbar_j = sum_{i in N(j)} w_ij * g_i, a gather over the same CSR
  * (valid because the contact graph is symmetric), plus the day's random
- * layer.  g, infbar: device double[N].  A graph with an agent-location
- * layer: GABM_EUNSUPPORTED. */
+ * layer and the agent-location layer (symmetric as well; same scratch rule
+ * as gabm_transmit_fwd).  g, infbar: device double[N]. */
 gabm_status gabm_transmit_bwd(gabm_graph g, const double *gvec, const gabm_rng *rng, int32_t day, double *infbar,
                               void *stream);
 

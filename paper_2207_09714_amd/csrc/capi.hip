@@ -8,6 +8,7 @@
 #include "agent.h"
 #include "batched.h"
 #include "day_kernels.h"
+#include "loc.h"
 #include "sim_internal.h"
 #include "tile.h"
 
@@ -84,6 +85,10 @@ struct StepInf {
     return T * (double)iota[(k < 1 ? 1 : (k > W ? W : k)) - 1];
   }
 };
+
+// the agent-location layer's two passes for one step, adding into `out`
+// (pressures in the graph's scratch)
+static void step_locations(const Graph& G, const StepInf& si, double* out, hipStream_t st);
 
 __global__ void __launch_bounds__(kBlock) k_step_gather(DGraph G, StepInf inf, double* out) {
   __shared__ TileShared sh;
@@ -308,7 +313,6 @@ gabm_status gabm_transmit_fwd(gabm_graph g, const void* inf, int32_t fmt, const 
   GABM_CHECK(fmt == GABM_INF_REC || fmt == GABM_INF_F32 || fmt == GABM_INF_F64 || fmt == GABM_INF_BIT1, GABM_EINVAL,
              "unknown inf format");
   const Graph& G = g->g;
-  GABM_CHECK(G.n_visits == 0, GABM_EUNSUPPORTED, "single-step sums do not cover the agent-location layer");
   DParams P;
   gabm_status rc = check_params(G, p, &P);
   if (rc != GABM_OK) return rc;
@@ -325,6 +329,7 @@ gabm_status gabm_transmit_fwd(gabm_graph g, const void* inf, int32_t fmt, const 
   if (dg.er_total > 0)
     hipLaunchKernelGGL(k_step_er, dim3(nblk(dg.er_total)), dim3(kBlock), 0, st, dg, rng_of(rng), rng->replicate, day,
                        si, A);
+  step_locations(G, si, A, st);
   if (lambda) hipLaunchKernelGGL(k_step_rate, dim3(nblk(G.N)), dim3(kBlock), 0, st, dg, P, set, day, A, lambda);
   GABM_HIP(hipGetLastError());
   return GABM_OK;
@@ -367,7 +372,6 @@ gabm_status gabm_transmit_bwd(gabm_graph g, const double* gvec, const gabm_rng* 
   GABM_CHECK(g && gvec && infbar && rng, GABM_EINVAL, "graph, g, infbar or rng is NULL");
   GABM_CHECK(day >= 0, GABM_ERANGE, "day must be >= 0");
   const Graph& G = g->g;
-  GABM_CHECK(G.n_visits == 0, GABM_EUNSUPPORTED, "single-step sums do not cover the agent-location layer");
   hipStream_t st = (hipStream_t)stream;
   StepInf si{gvec, GABM_INF_F64, 0.0, 0.0};
   const DGraph dg = G.view();
@@ -375,9 +379,24 @@ gabm_status gabm_transmit_bwd(gabm_graph g, const double* gvec, const gabm_rng* 
   if (dg.er_total > 0)
     hipLaunchKernelGGL(k_step_er, dim3(nblk(dg.er_total)), dim3(kBlock), 0, st, dg, rng_of(rng), rng->replicate, day,
                        si, infbar);
+  step_locations(G, si, infbar, st);
   GABM_HIP(hipGetLastError());
   return GABM_OK;
 }
+
+namespace gabm {
+static void step_locations(const Graph& G, const StepInf& si, double* out, hipStream_t st) {
+  if (G.n_visits == 0) return;
+  LocView L;
+  L.N = G.N; L.n_loc = G.n_loc; L.V = G.n_visits;
+  L.lv_agent = G.lv_agent; L.lv_loc = G.lv_loc; L.lv_w = G.lv_w;
+  L.av_ptr = G.av_ptr; L.av_loc = G.av_loc; L.av_w = G.av_w;
+  hipLaunchKernelGGL(k_fill_f64, dim3(nblk(G.n_loc)), dim3(kBlock), 0, st, G.loc_scratch, (int64_t)G.n_loc);
+  hipLaunchKernelGGL(k_loc_pressure<StepInf>, dim3(nblk(G.n_visits)), dim3(kBlock), 0, st, L, si, G.loc_scratch);
+  hipLaunchKernelGGL(k_loc_gather<StepInf>, dim3(nblk(std::max<int64_t>(G.N, G.n_loc))), dim3(kBlock), 0, st, L, si,
+                     (const double*)G.loc_scratch, out, G.loc_scratch + G.n_loc);
+}
+}  // namespace gabm
 
 gabm_status gabm_param_grad_reduce(gabm_graph g, const double* lambda_bar, const double* A, const gabm_params* p,
                                    int32_t set, int32_t day, double* dR, double* dS, void* stream) {

@@ -62,6 +62,7 @@ struct Graph {
   int64_t* av_ptr = nullptr;    // [N+1] visits of agent i: av_ptr[i] .. av_ptr[i+1]
   int32_t* av_loc = nullptr;    // [V]
   float* av_w = nullptr;        // [V]
+  double* loc_scratch = nullptr;  // [2 * n_loc] pressures of the single-step sums
   bool has_er() const { return !er_off_h.empty() && er_off_h.back() > 0; }
   // a layer whose sums arrive through the per-agent accumulators (daily random
   // pairs, or locations)

@@ -422,6 +422,8 @@ void Graph::release() {
   age = nullptr; pop_of = nullptr;
   pop_off = nullptr; er_off = nullptr;
   hipFree(lv_agent); hipFree(lv_loc); hipFree(lv_w); hipFree(av_ptr); hipFree(av_loc); hipFree(av_w);
+  hipFree(loc_scratch);
+  loc_scratch = nullptr;
   lv_agent = nullptr; lv_loc = nullptr; lv_w = nullptr; av_ptr = nullptr; av_loc = nullptr; av_w = nullptr;
   n_loc = 0; n_visits = 0;
 }
@@ -600,6 +602,7 @@ static gabm_status build_locations(const gabm_graph_desc* d, hipStream_t st, Gra
   GABM_HIP(dalloc(&G.av_ptr, (size_t)N + 1));
   GABM_HIP(dalloc(&G.av_loc, V));
   GABM_HIP(dalloc(&G.av_w, V));
+  GABM_HIP(dalloc(&G.loc_scratch, (size_t)2 * L));
   GABM_HIP(hipMemcpyAsync(G.lv_agent, lv_a.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
   GABM_HIP(hipMemcpyAsync(G.lv_loc, lv_l.data(), sizeof(int32_t) * V, hipMemcpyHostToDevice, st));
   GABM_HIP(hipMemcpyAsync(G.lv_w, lv_wh.data(), sizeof(float) * V, hipMemcpyHostToDevice, st));

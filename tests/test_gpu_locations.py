@@ -245,17 +245,40 @@ def test_location_argument_checks(G):
         G.Graph(n_agents=n, src=wl.src[sel], dst=wl.dst[sel], w=wl.w[sel], age=wl.pop.age, visits=cross,
                 pop_offsets=two)
     assert e.value.code == L.ERANGE
-    # batched runs and the single-step sums do not take the layer
+    # batched runs do not take the layer
     g = build(good)
     with pytest.raises(L.GabmError) as e:
         G.Simulator(g, n_sets=2, K=wl.K, Z=wl.Z, mode=G.HARD_ST)
     assert e.value.code == L.EUNSUPPORTED
-    pb = G.ParamBlock(R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=wl.Z, K=wl.K, n_sets=1, mode=G.PLAIN)
-    A = torch.zeros(n, dtype=torch.float64, device="cuda")
-    inf = torch.zeros(n, dtype=torch.float32, device="cuda")
-    with pytest.raises(L.GabmError) as e:
-        G.transmit_fwd(g, inf, 1, pb, 0, G.make_rng(1), 0, A)
-    assert e.value.code == L.EUNSUPPORTED
+
+
+def test_single_step_sums_with_locations(G, O):
+    """gabm_transmit_fwd from day-0 records on a graph with contacts, the
+    daily random layer and venues equals the oracle's day-0 sums bit for bit;
+    gabm_transmit_bwd of a vector equals the forward sum of the same vector
+    (every layer is symmetric), exactly for dyadic values."""
+    wl = make_workload("c2", n_agents=6000, K=4)
+    visits, nl, Z = with_visits(wl)
+    g = graph_of(G, wl, visits, nl)
+    ref = O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=wl.R[0],
+                S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=Z, T=wl.T, mode=O.PLAIN, seed=wl.seed,
+                er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, want_agents=True, want_stage=True,
+                visits=visits)
+    st0 = ref["stage"][0].astype(np.uint32)
+    rec = np.where(st0 == 2, 2 | (5 << 8) | (0xFFFF << 16), 0 | (0xFFFF << 16)).astype(np.uint32)
+    pb = G.ParamBlock(R=wl.R, S=wl.S, m=wl.m, i0=wl.i0, Z=Z, K=wl.K, n_sets=1, mode=G.PLAIN, T=wl.T)
+    rng = G.make_rng(wl.seed)
+    A = torch.zeros(wl.n_agents, dtype=torch.float64, device="cuda")
+    G.transmit_fwd(g, torch.tensor(rec.view(np.int32), device="cuda"), 0, pb, 0, rng, 0, A)
+    torch.cuda.synchronize()
+    assert np.array_equal(A.cpu().numpy(), ref["A"][0])
+    gv = torch.tensor(np.random.default_rng(3).integers(-512, 513, wl.n_agents) / 1024.0, device="cuda")
+    fwd = torch.zeros_like(gv)
+    bwd = torch.zeros_like(gv)
+    G.transmit_fwd(g, gv, 2, pb, 0, rng, 1, fwd)
+    G.transmit_bwd(g, gv, rng, 1, bwd)
+    torch.cuda.synchronize()
+    assert torch.equal(fwd, bwd) and float(fwd.abs().max()) > 0
 
 
 def test_location_layer_hip_graph_replays_and_timing(G):
