@@ -292,7 +292,7 @@ int ora_run(const ora_cfg *c, ora_out *o) {
   if (mode == ORA_PLAIN && nd > 0) return -5;
   if (c->pop_offsets[0] != 0 || c->pop_offsets[c->n_pops] != n) return -6;
   const int dwell = c->dwell_E != NULL || c->dwell_I != NULL;
-  if (dwell && (!c->dwell_E || !c->dwell_I || tE > 8 || tI > 8 || c->iota)) return -8;
+  if (dwell && (!c->dwell_E || !c->dwell_I || tE > 8 || tI > 8)) return -8;
   /* dwell tangents; relaxed windows in the forward (SOFT); either needs the relaxed one-hots */
   const int ddw = dwell && nd > 0 && (c->ddwE || c->ddwI);
   const int rel_fwd = dwell && mode == ORA_SOFT;
@@ -502,15 +502,15 @@ int ora_run(const ora_cfg *c, ora_out *o) {
           if (ddw && ws.xi[sl] != 0.0) { /* the windows' own tangent along the dwell log weights */
             double a, b, r;
             dwell_dw(&ws, c, rel_fwd, sl, d, k, tau, &a, &b, &r);
-            dE += a * ws.xi[sl];
-            dI += b * ws.xi[sl];
+            dE += IOTA(k) * (a * ws.xi[sl]);
+            dI += IOTA(k) * (b * ws.xi[sl]);
           }
         }
         if (i0W != 0.0) dI += IOTA(t + tE + 1) * (i0W * ws.dx0[(size_t)d * n + j]);
         if (ddw && ws.x0[j] != 0.0) {
           double a, r;
           init_dw(&ws, c, j, d, t, tau, &a, &r);
-          dI += a * ws.x0[j];
+          if (a != 0.0) dI += IOTA(t + tE + 1) * (a * ws.x0[j]); /* zero once t >= tau_I */
         }
         ws.dinf[(size_t)d * n + j] = TE * dE + TI * dI;
       }

@@ -86,7 +86,9 @@ typedef struct {
    * are then the longest lengths), or NULL for the fixed tau_E / tau_I.  Each
    * exposure of agent i on day u has its lengths drawn by Gumbel-max with the
    * uniforms of (i, u); an initial infection's I length uses day 2^32 - 1.
-   * Not combined with an infectiousness profile. */
+   * With an infectiousness profile (of tau_E + tau_I days) the days since
+   * exposure keep their meaning: an exposure k days back weighs iota[k-1],
+   * an initial infection t + tau_E + 1 days back. */
   const float *dwell_E, *dwell_I;
   /* tangent directions of the dwell log weights, [ndir*tau_E] and
    * [ndir*tau_I], or NULL (zero).  The drawn lengths get the straight-through

@@ -624,30 +624,29 @@ def test_dwell_stage_durations_follow_the_draws():
 
 def test_dwell_tables_are_checked():
     wl = make_workload("c1", n_agents=500, K=5)
-    with pytest.raises(ValueError):  # not combined with an infectiousness profile
-        O.run_workload(wl, mode=O.PLAIN, dwell=(np.zeros(3, np.float32), np.zeros(5, np.float32)),
-                       iota=np.ones(8, np.float32))
     with pytest.raises(ValueError):  # lengths of at most 8 days
         O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=2.5,
               S=wl.S[0], m=0.01, i0=0.01, Z=wl.Z, tau_E=9, tau_I=5,
               dwell=(np.zeros(9, np.float32), np.zeros(5, np.float32)))
 
 
-def test_soft_dwell_weight_tangents_match_finite_differences():
+@pytest.mark.parametrize("iota", [None, PROFILE], ids=["flat", "profile"])
+def test_soft_dwell_weight_tangents_match_finite_differences(iota):
     """Relaxed mode with dwell tables: the relaxed one-hots of the Gumbel-max
     draws weight a mixture of windows, so the loss is smooth in the log weights
-    and the tangents along each of them equal central differences."""
+    and the tangents along each of them equal central differences (also with
+    an infectiousness profile over days since exposure)."""
     wl, tgt = _soft_setup()
     K = wl.K
     dirs = O.dwell_directions(K, 8, 3, 5)
-    r = O.run_workload(wl, mode=O.SOFT, target=tgt, directions=dirs, dwell=DWELL)
+    r = O.run_workload(wl, mode=O.SOFT, target=tgt, directions=dirs, dwell=DWELL, iota=iota)
     g = r["dL"][11:]
     assert np.all(np.isfinite(g)) and np.max(np.abs(g)) > 0
 
     def loss_at(which, k, delta):
         lw = [DWELL[0].copy(), DWELL[1].copy()]
         lw[which][k] = np.float32(lw[which][k] + delta)
-        return O.run_workload(wl, mode=O.SOFT, target=tgt, dwell=tuple(lw))["loss"]
+        return O.run_workload(wl, mode=O.SOFT, target=tgt, dwell=tuple(lw), iota=iota)["loss"]
 
     h = 2.0**-8
     gmax = np.max(np.abs(g))
