@@ -186,9 +186,10 @@ typedef struct {
                           (-inf: never), or both NULL for fixed tau_E / tau_I.  Each exposure of an
                           agent on day u draws both lengths by Gumbel-max, argmax_k lw[k] -
                           log(-log u_k), with Philox uniforms of (agent, u) (an initial infection's
-                          I length: day 2^32 - 1); tau_E, tau_I <= 8 (GABM_EINVAL otherwise).  Hard
-                          modes only, no profile, B = 1 (GABM_EUNSUPPORTED otherwise).  NaN weights
-                          are undefined. */
+                          I length: day 2^32 - 1); tau_E, tau_I <= 8 (GABM_EINVAL otherwise).  With
+                          a profile, days since exposure keep their meaning (iota has tau_E + tau_I
+                          values).  Hard modes only, B = 1 (GABM_EUNSUPPORTED otherwise).  NaN
+                          weights are undefined. */
   const float *dwell_I;
 } gabm_params;
 

@@ -56,7 +56,6 @@ gabm_status check_params(const Graph& G, const gabm_params* p, DParams* out) {
              "dwell_E and dwell_I are given together or not at all");
   if (p->dwell_E) {
     GABM_CHECK(p->tau_E <= 8 && p->tau_I <= 8, GABM_EINVAL, "dwell tables cover at most 8 days each");
-    GABM_CHECK(p->iota == nullptr, GABM_EUNSUPPORTED, "dwell tables are not combined with an infectiousness profile");
     GABM_CHECK(p->mode != GABM_SOFT, GABM_EUNSUPPORTED, "dwell tables run in the hard modes (PLAIN, HARD_ST)");
   }
   P.dwell_E = p->dwell_E;

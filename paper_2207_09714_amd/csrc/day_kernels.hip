@@ -438,7 +438,8 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           const int bS = dwell_relaxed(P.dwell_I, P.tau_I, a.rng, loc, (uint32_t)d, TAG_DWELL_I, (uint32_t)p, a.stream,
                                        P.tau, cI);
           pre[0] = 0.0;
-          for (int k = 1; k <= W; ++k) pre[k] = pre[k - 1] + (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
+          for (int k = 1; k <= W; ++k)
+            pre[k] = pre[k - 1] + iota_at(P, k) * (double)a.ring[(int64_t)((d + k) % W) * G.N + i];
           auto DR = [&](int x) { return d + x < P.K ? m * a.Dbar[(int64_t)o * P.K + d + x] : 0.0; };
           dwell_sensitivities(P, pre, aS, bS, DR, gE, gI);
           st_categorical(cE, gE, P.tau_E, P.tau, sdw);
@@ -478,7 +479,7 @@ __global__ void __launch_bounds__(kBlock) k_day_bwd(BwdArgs<RT> a) {
           dwell_relaxed(P.dwell_I, P.tau_I, a.rng, loc, kDayInit, TAG_DWELL_I, (uint32_t)p, a.stream, P.tau, cI);
           double run = 0.0;
           for (int b = 1; b <= P.tau_I; ++b) {
-            run += (double)a.ring[(int64_t)((b - 1) % W) * G.N + i];
+            run += iota_at(P, P.tau_E + b) * (double)a.ring[(int64_t)((b - 1) % W) * G.N + i];
             gI[b - 1] = P.TI * run + (b - 1 < P.K ? m * a.Dbar[(int64_t)o * P.K + b - 1] : 0.0);
           }
           st_categorical(cI, gI, P.tau_I, P.tau, sdw + 8);

@@ -162,7 +162,6 @@ def test_dwell_argument_checks(G):
         return e.value.code
 
     assert code(mode=G.SOFT, dwell=DWELL) == L.EUNSUPPORTED
-    assert code(mode=G.HARD_ST, dwell=DWELL, iota=np.ones(8, np.float32)) == L.EUNSUPPORTED
     assert code(mode=G.HARD_ST, tau_E=9, dwell=(np.zeros(9, np.float32), DWELL[1])) == L.EINVAL
     with pytest.raises(ValueError):
         G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.HARD_ST, dwell=(DWELL[0], DWELL[1][:4]))
@@ -236,3 +235,31 @@ def test_dwell_weight_gradients_on_packed_populations(G, O):
                for p in range(P))
     got = np.concatenate([gr["ddwell_E"].cpu().numpy(), gr["ddwell_I"].cpu().numpy()])
     assert_grads(got, want)
+
+
+PROFILE = np.array([0.25, 0.5, 0.75, 1.5, 1.75, 1.25, 0.75, 0.25], np.float32)
+
+
+def test_dwell_with_profile_matches_oracle(G, O):
+    """Drawn dwell times with an infectiousness profile over days since
+    exposure and presymptomatic transmission (receiver-tile kernels): counts
+    bit-exact, gradients with respect to R, S, m, i0 and the dwell log weights
+    against the oracle's tangents."""
+    wl = make_workload("c2", n_agents=6000, K=30)
+    tgt = np.linspace(0.0, 0.6, wl.K)
+    _say(f"dwell with profile N={wl.n_agents} K={wl.K}")
+    g = graph_of(G, wl)
+    sim = G.Simulator(g, K=wl.K, Z=wl.Z, mode=G.HARD_ST, ckpt_every=7, T=T_PRE, tau_g=wl.tau_g, dwell=DWELL,
+                      iota=PROFILE)
+    pb = sim.params(wl.R, wl.S, wl.m, wl.i0)
+    out = sim.forward(pb, seed=wl.seed, target=torch.tensor(tgt, device="cuda"))
+    gr = sim.backward(pb, seed=wl.seed)
+    ref = O.run(age=wl.pop.age, pop_offsets=wl.pop.pop_offsets, src=wl.src, dst=wl.dst, w=wl.w, K=wl.K, R=wl.R[0],
+                S=wl.S[0], m=wl.m[0], i0=wl.i0[0], Z=wl.Z, T=np.asarray(T_PRE, np.float32), mode=O.HARD_ST,
+                tau_g=wl.tau_g, seed=wl.seed, er_mean_deg=wl.er_mean_deg, er_weight=wl.er_weight, target=tgt,
+                directions=O.dwell_directions(wl.K, 8, 3, 5), dwell=DWELL, iota=PROFILE)
+    assert np.array_equal(out["counts"][0].cpu().numpy(), ref["counts"])
+    assert ref["mismatch"] == 0
+    assert_grads(grads_vec(gr), ref["dL"][:11])
+    got = np.concatenate([gr["ddwell_E"].cpu().numpy(), gr["ddwell_I"].cpu().numpy()])
+    assert_grads(got, ref["dL"][11:])
